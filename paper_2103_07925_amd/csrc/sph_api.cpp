@@ -1,0 +1,1063 @@
+// sph_api.cpp -- host implementation of the C ABI declared in include/sphrb.h.
+//
+// Owns no device memory: every device array of a scene is carved out of the
+// caller's arena.  Set-up bookkeeping (validation, layout, slot order,
+// material constants, time step) runs on the host; every step of the
+// method runs in the kernels of sph_kernels.hip, enqueued on the scene's
+// stream without host round trips.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sphrb.h"
+#include "sph_internal.h"
+
+using namespace sphrb;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                 \
+  do {                                                                                \
+    hipError_t _e = (expr);                                                           \
+    if (_e != hipSuccess) return fail(SPH_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kGlobalBlocks = 256;
+
+size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+// Arena carving: the same sequence of requests sizes the arena and places
+// the arrays in it.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = align_up(off);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += sizeof(T) * (count > 0 ? count : 1);
+    return p;
+  }
+};
+
+double sigma_d(int dim) {
+  if (dim == 2) return 7.0 / (478.0 * kPi);
+  return 1.0 / (120.0 * kPi);
+}
+double powi(double h, int d) {
+  double r = h;
+  for (int k = 1; k < d; ++k) r = r * h;
+  return r;
+}
+
+}  // namespace
+
+struct sph_scene {
+  Params P;
+  int precision;
+  hipStream_t stream;
+  char* arena;
+  size_t arena_bytes;
+  int64_t step;
+  int64_t n_fluid, n_wall;
+  // buffers (typed as void* / raw; cast by precision)
+  void* pos[2];
+  uint32_t* cell[2];
+  void* u[2];
+  void* a[2];
+  void* T[2];
+  void* m[2];
+  uint32_t* id[2];
+  uint32_t* info[2];
+  int32_t* aux[2];
+  int ip, iu, iT;
+  void *rho, *p, *pw, *uw, *dTdt;
+  SortBufs sb;
+  uint32_t* cstart;
+  V4<double> *s_rb, *s_rk, *s_f, *s_aw, *s_x;
+  double* s_m;
+  int32_t *s_sorted, *s_body;
+  uint32_t* s_id;
+  V4<double> *w_x0, *w_aw;
+  int32_t* w_sorted;
+  Body* bodies;
+  void* mat;
+  uint32_t* err;
+  unsigned long long* pairs;
+  double* gpart;
+  double* gout;
+  // timers
+  int timers;
+  hipEvent_t ev[5];
+  double t_nb, t_sweep, t_body, t_other;
+};
+
+namespace {
+
+int validate(const sph_scene_desc* d) {
+  if (!d) return fail(SPH_E_INVALID, "null descriptor");
+  if (d->dim != 2 && d->dim != 3) return fail(SPH_E_INVALID, "dim must be 2 or 3");
+  if (d->precision != SPH_FP64 && d->precision != SPH_FP32_SWEEP) return fail(SPH_E_INVALID, "bad precision");
+  if (!(d->dx > 0.0) || !std::isfinite(d->dx)) return fail(SPH_E_INVALID, "dx must be positive");
+  if (d->n < 0 || d->n > 0x7fffffffLL) return fail(SPH_E_INVALID, "particle count out of range");
+  if (d->n > 0 && (!d->x || !d->u || !d->kind || !d->phase)) return fail(SPH_E_INVALID, "missing particle arrays");
+  if (d->n_mat <= 0 || d->n_mat > 256 || !d->mat) return fail(SPH_E_INVALID, "1..256 materials required");
+  if (d->n_body < 0 || (d->n_body > 0 && !d->bodies)) return fail(SPH_E_INVALID, "bad bodies");
+  if (std::max(d->max_bodies, d->n_body) > 65534) return fail(SPH_E_INVALID, "too many bodies");
+  double rc = 3.0 * d->dx;
+  double L = d->cell_edge > 0.0 ? d->cell_edge : rc;
+  if (L < rc) return fail(SPH_E_INVALID, "cell edge must be at least r_c = 3 dx");
+  for (int a = 0; a < d->dim; ++a)
+    if (!(d->hi[a] > d->lo[a])) return fail(SPH_E_INVALID, "empty domain");
+  for (int k = 0; k < d->n_mat; ++k) {
+    const sph_material& M = d->mat[k];
+    if (!(M.rho0 > 0.0)) return fail(SPH_E_INVALID, "material density must be positive");
+    if (M.switch_to >= d->n_mat) return fail(SPH_E_INVALID, "switch_to out of range");
+  }
+  for (int64_t i = 0; i < d->n; ++i) {
+    int k = d->kind[i];
+    if (k < 0 || k > 2) return fail(SPH_E_INVALID, "bad kind at " + std::to_string(i));
+    if (d->phase[i] < 0 || d->phase[i] >= d->n_mat) return fail(SPH_E_INVALID, "bad phase at " + std::to_string(i));
+    if (k == SPH_RIGID && (!d->body || d->body[i] < 0 || d->body[i] >= d->n_body))
+      return fail(SPH_E_INVALID, "bad body at " + std::to_string(i));
+    if (k == SPH_FLUID && d->mat[d->phase[i]].p0 <= 0.0)
+      return fail(SPH_E_INVALID, "fluid phase needs p0 > 0");
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(d->x[3 * i + a]) || !std::isfinite(d->u[3 * i + a]))
+        return fail(SPH_E_INVALID, "non-finite input at " + std::to_string(i));
+  }
+  return SPH_OK;
+}
+
+// Eq. nummeth_timint_timestepcond evaluated at t = 0: CFL with the fastest
+// speed of sound among fluid phases present and the largest initial fluid
+// speed, viscous and body-force bounds, conduction when thermal.  The
+// contact bound is used only for a given stiffness.
+double time_step(const sph_scene_desc* d, double* m_min) {
+  const double h = d->dx;
+  const double vol0 = powi(d->dx, d->dim);
+  std::vector<char> fl(d->n_mat, 0), rg(d->n_mat, 0);
+  double umax = 0.0;
+  for (int64_t i = 0; i < d->n; ++i) {
+    if (d->kind[i] == SPH_FLUID) {
+      fl[d->phase[i]] = 1;
+      const double* u = &d->u[3 * i];
+      double s = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+      if (s > umax) umax = s;
+    } else if (d->kind[i] == SPH_RIGID) {
+      rg[d->phase[i]] = 1;
+    }
+  }
+  double cmax = 0.0, numax = 0.0, bmax = 0.0, heat = INFINITY, mmin = INFINITY;
+  for (int k = 0; k < d->n_mat; ++k) {
+    const sph_material& M = d->mat[k];
+    if (fl[k]) {
+      cmax = std::max(cmax, std::sqrt(M.p0 / M.rho0));
+      numax = std::max(numax, M.nu);
+    }
+    if (fl[k] || rg[k]) {
+      bmax = std::max(bmax, std::sqrt(M.b[0] * M.b[0] + M.b[1] * M.b[1] + M.b[2] * M.b[2]));
+      if (d->thermal && M.kappa > 0.0) heat = std::min(heat, 0.1 * M.rho0 * M.cp * h * h / M.kappa);
+    }
+    if (rg[k]) mmin = std::min(mmin, M.rho0 * vol0);
+  }
+  double dt = INFINITY;
+  if (cmax > 0.0) dt = std::min(dt, 0.25 * h / (cmax + umax));
+  if (numax > 0.0) dt = std::min(dt, 0.125 * h * h / numax);
+  if (bmax > 0.0) dt = std::min(dt, 0.25 * std::sqrt(h / bmax));
+  dt = std::min(dt, heat);
+  *m_min = mmin;
+  return dt;
+}
+
+struct Counts {
+  int64_t n_rigid = 0, n_moving = 0, n_fluid = 0, n_wall = 0;
+};
+
+Counts count(const sph_scene_desc* d) {
+  Counts c;
+  for (int64_t i = 0; i < d->n; ++i) {
+    if (d->kind[i] == SPH_RIGID) c.n_rigid++;
+    else if (d->kind[i] == SPH_FLUID) c.n_fluid++;
+    else {
+      c.n_wall++;
+      if (d->moving && d->moving[i]) c.n_moving++;
+    }
+  }
+  return c;
+}
+
+template <typename R>
+void carve(Carver& cv, sph_scene* s, const Params& P, int64_t nmat) {
+  const size_t n = (size_t)P.n;
+  for (int b = 0; b < 2; ++b) {
+    s->pos[b] = cv.take<V4<R>>(n);
+    s->cell[b] = cv.take<uint32_t>(n);
+    s->u[b] = cv.take<V4<R>>(n);
+    s->a[b] = cv.take<V4<R>>(n);
+    s->T[b] = cv.take<R>(n);
+    s->m[b] = cv.take<R>(n);
+    s->id[b] = cv.take<uint32_t>(n);
+    s->info[b] = cv.take<uint32_t>(n);
+    s->aux[b] = cv.take<int32_t>(n);
+  }
+  s->rho = cv.take<R>(n);
+  s->p = cv.take<R>(n);
+  s->pw = cv.take<R>(n);
+  s->uw = cv.take<V4<R>>(n);
+  s->dTdt = cv.take<R>(n);
+  s->sb.key = cv.take<uint32_t>(n);
+  s->sb.rank = cv.take<uint32_t>(n);
+  s->sb.tid = cv.take<uint32_t>(n);
+  s->sb.tsrc = cv.take<uint32_t>(n);
+  s->sb.perm = cv.take<uint32_t>(n);
+  s->sb.ccount = cv.take<uint32_t>((size_t)P.ncells);
+  s->sb.nbsum = (P.ncells + 1023) / 1024;
+  s->sb.bsum = cv.take<uint32_t>((size_t)s->sb.nbsum + 1);
+  s->cstart = cv.take<uint32_t>((size_t)P.ncells + 1);
+  const size_t nr = (size_t)P.n_rigid, nw = (size_t)P.n_moving;
+  s->s_rb = cv.take<V4<double>>(nr);
+  s->s_rk = cv.take<V4<double>>(nr);
+  s->s_f = cv.take<V4<double>>(nr);
+  s->s_aw = cv.take<V4<double>>(nr);
+  s->s_x = cv.take<V4<double>>(nr);
+  s->s_m = cv.take<double>(nr);
+  s->s_sorted = cv.take<int32_t>(nr);
+  s->s_body = cv.take<int32_t>(nr);
+  s->s_id = cv.take<uint32_t>(nr);
+  s->w_x0 = cv.take<V4<double>>(nw);
+  s->w_aw = cv.take<V4<double>>(nw);
+  s->w_sorted = cv.take<int32_t>(nw);
+  s->bodies = cv.take<Body>((size_t)std::max(P.maxb, 1));
+  s->mat = cv.take<MatT<R>>((size_t)nmat);
+  s->err = cv.take<uint32_t>(4);
+  s->pairs = cv.take<unsigned long long>(2);
+  s->gpart = cv.take<double>(5 * kGlobalBlocks);
+  s->gout = cv.take<double>(8);
+}
+
+int make_params(const sph_scene_desc* d, Params& P, double* m_min) {
+  std::memset(&P, 0, sizeof(P));
+  P.dim = d->dim;
+  P.n = d->n;
+  P.dx = d->dx;
+  P.h = d->dx;
+  P.rc = 3.0 * P.h;
+  P.rc2 = P.rc * P.rc;
+  P.L = d->cell_edge > 0.0 ? d->cell_edge : P.rc;
+  P.ncells = 1;
+  for (int a = 0; a < 3; ++a) {
+    P.lo[a] = d->lo[a];
+    if (a < d->dim) {
+      double ext = d->hi[a] - d->lo[a];
+      int nc = (int)std::ceil(ext / P.L * (1.0 - 1e-12));
+      P.nc[a] = nc < 1 ? 1 : nc;
+    } else {
+      P.nc[a] = 1;
+      P.lo[a] = 0.0;
+    }
+    P.ncells *= P.nc[a];
+  }
+  if (P.ncells > 0x7fffffffLL) return fail(SPH_E_INVALID, "cell grid too large");
+  const double sg = sigma_d(d->dim);
+  P.wnorm = sg / powi(P.h, d->dim);
+  P.dnorm = -5.0 * sg / powi(P.h, d->dim + 1);
+  P.vol0 = powi(d->dx, d->dim);
+  if (d->dim == 2) {
+    double reff2 = d->dx * d->dx / kPi;
+    P.Ir_fac = 0.5 * reff2;
+  } else {
+    double reff = std::cbrt(0.75 / kPi) * d->dx;
+    P.Ir_fac = 0.4 * (reff * reff);
+  }
+  double mmin;
+  double dt0 = time_step(d, &mmin);
+  double dt = dt0;
+  if (d->contact && d->k_c > 0.0 && std::isfinite(mmin)) dt = std::min(dt, 0.22 * std::sqrt(mmin / d->k_c));
+  P.dt = d->dt > 0.0 ? d->dt : dt;
+  if (!(P.dt > 0.0) || !std::isfinite(P.dt)) return fail(SPH_E_INVALID, "no finite time step");
+  P.hdt = 0.5 * P.dt;
+  if (d->k_c >= 0.0) P.kc = d->k_c;
+  else if (std::isfinite(mmin)) {
+    double b = 0.22 / (2.0 * (d->dt > 0.0 ? d->dt : dt0));
+    P.kc = mmin * (b * b);
+  } else P.kc = 0.0;
+  if (d->d_c >= 0.0) P.dc = d->d_c;
+  else P.dc = std::isfinite(mmin) ? 0.2 * std::sqrt(P.kc * mmin / 2.0) : 0.0;
+  P.thermal = d->thermal;
+  P.contact = d->contact;
+  P.pswitch = d->phase_switch;
+  P.wall_A = d->wall_A;
+  P.wall_Om = d->wall_Omega;
+  for (int a = 0; a < 3; ++a) P.wall_dir[a] = d->wall_dir[a];
+  P.heat_src = d->heat_src;
+  P.sQ = d->src_Q;
+  P.ssig = d->src_sigma;
+  for (int a = 0; a < 2; ++a) { P.ss0[a] = d->src_s0[a]; P.sv[a] = d->src_v[a]; }
+  P.sztop = d->src_ztop;
+  P.sdepth = d->src_depth;
+  P.n_mat = d->n_mat;
+  P.nb = d->n_body;
+  P.maxb = std::max(d->max_bodies, d->n_body);
+  Counts c = count(d);
+  P.n_rigid = c.n_rigid;
+  P.n_moving = c.n_moving;
+  *m_min = mmin;
+  return SPH_OK;
+}
+
+template <typename R>
+KC<R> make_kc(const Params& P) {
+  KC<R> k;
+  k.h = (R)P.h;
+  k.inv_h = (R)(1.0 / P.h);
+  k.wnorm = (R)P.wnorm;
+  k.dnorm = (R)P.dnorm;
+  k.rc2 = (R)P.rc2;
+  k.L = (R)P.L;
+  k.dx = (R)P.dx;
+  k.dx2 = (R)(P.dx * P.dx);
+  k.vol0 = (R)P.vol0;
+  k.kc = (R)P.kc;
+  k.dc = (R)P.dc;
+  k.dt = (R)P.dt;
+  k.hdt = (R)P.hdt;
+  for (int a = 0; a < 3; ++a) k.lo[a] = (R)P.lo[a];
+  return k;
+}
+
+template <typename R>
+View<R> make_view(sph_scene* s, int ip, int iu, int iT) {
+  View<R> v;
+  v.pos = (V4<R>*)s->pos[ip];
+  v.cell = s->cell[ip];
+  v.u = (V4<R>*)s->u[iu];
+  v.a = (V4<R>*)s->a[ip];
+  v.T = (R*)s->T[iT];
+  v.m = (R*)s->m[ip];
+  v.id = s->id[ip];
+  v.info = s->info[ip];
+  v.aux = s->aux[ip];
+  v.u_out = (V4<R>*)s->u[1 - iu];
+  v.T_out = (R*)s->T[1 - iT];
+  v.rho = (R*)s->rho;
+  v.p = (R*)s->p;
+  v.pw = (R*)s->pw;
+  v.uw = (V4<R>*)s->uw;
+  v.dTdt = (R*)s->dTdt;
+  v.cstart = s->cstart;
+  v.s_rb = s->s_rb;
+  v.s_rk = s->s_rk;
+  v.s_f = s->s_f;
+  v.s_aw = s->s_aw;
+  v.s_x = s->s_x;
+  v.s_m = s->s_m;
+  v.s_sorted = s->s_sorted;
+  v.s_body = s->s_body;
+  v.s_id = s->s_id;
+  v.w_x0 = s->w_x0;
+  v.w_aw = s->w_aw;
+  v.w_sorted = s->w_sorted;
+  v.mat = (const MatT<R>*)s->mat;
+  v.bodies = s->bodies;
+  v.err = s->err;
+  v.pairs = s->pairs;
+  return v;
+}
+
+template <typename R>
+View<R> cur(sph_scene* s) {
+  return make_view<R>(s, s->ip, s->iu, s->iT);
+}
+
+void zero_pairs(sph_scene* s, bool total) {
+  launch_fill_u32(reinterpret_cast<uint32_t*>(s->pairs), 0u, total ? 4 : 2, s->stream);
+}
+
+// counting sort by (cell, id) of the current buffers into the other set
+template <typename R>
+void sort_and_permute(sph_scene* s) {
+  View<R> src = cur<R>(s);
+  launch_sort_keys(s->P, s->sb, s->cstart, src.id, s->stream);
+  View<R> dst = make_view<R>(s, 1 - s->ip, 1 - s->iu, 1 - s->iT);
+  Launch<R>::gather(src, dst, s->P, s->sb, s->stream);
+  s->ip = 1 - s->ip;
+  s->iu = 1 - s->iu;
+  s->iT = 1 - s->iT;
+}
+
+// densities, extrapolation, forces (+ heat), body sums
+template <typename R>
+void evaluate(sph_scene* s, int kick, int heat, double t) {
+  const KC<R> k = make_kc<R>(s->P);
+  View<R> v = cur<R>(s);
+  Launch<R>::density(v, s->P, k, s->stream);
+  Launch<R>::extrapolate(v, s->P, k, s->stream);
+  Launch<R>::forces(v, s->P, k, kick, heat, t, s->stream);
+  s->iu = 1 - s->iu;
+  if (s->P.thermal) s->iT = 1 - s->iT;
+  if (s->timers) (void)hipEventRecord(s->ev[3], s->stream);
+  launch_body_reduce(s->bodies, s->s_f, s->s_rk, s->P, kick, s->stream);
+}
+
+template <typename R>
+void one_step(sph_scene* s) {
+  const Params& P = s->P;
+  const KC<R> k = make_kc<R>(P);
+  const double t_new = (double)(s->step + 1) * P.dt;
+  zero_pairs(s, false);
+  if (s->timers) (void)hipEventRecord(s->ev[0], s->stream);
+  View<R> v = cur<R>(s);
+  Launch<R>::kick_drift(v, P, k, s->sb, s->stream);
+  launch_body_kick_drift(s->bodies, P, s->stream);
+  Launch<R>::rigid_pose(v, P, k, s->sb, t_new, s->stream);
+  Launch<R>::wall_motion(v, P, k, s->sb, t_new, s->stream);
+  if (s->timers) (void)hipEventRecord(s->ev[1], s->stream);
+  sort_and_permute<R>(s);
+  if (s->timers) (void)hipEventRecord(s->ev[2], s->stream);
+  evaluate<R>(s, 1, 1, t_new);
+  v = cur<R>(s);
+  Launch<R>::rigid_velocity(v, P, s->stream);
+  if (s->timers) {
+    (void)hipEventRecord(s->ev[4], s->stream);
+    (void)hipEventSynchronize(s->ev[4]);
+    float a = 0, b = 0, c = 0, d = 0;
+    (void)hipEventElapsedTime(&a, s->ev[0], s->ev[1]);
+    (void)hipEventElapsedTime(&b, s->ev[1], s->ev[2]);
+    (void)hipEventElapsedTime(&c, s->ev[2], s->ev[3]);
+    (void)hipEventElapsedTime(&d, s->ev[3], s->ev[4]);
+    s->t_other += a;
+    s->t_nb += b;
+    s->t_sweep += c;
+    s->t_body += d;
+  }
+  s->step += 1;
+}
+
+template <typename R>
+int create_impl(const sph_scene_desc* d, sph_scene* s) {
+  const Params& P = s->P;
+  const int64_t n = P.n;
+  hipStream_t st = s->stream;
+  // host-side initial arrays in original-id order
+  std::vector<V4<R>> pos(n), u(n), a(n);
+  std::vector<uint32_t> cell(n), id(n), info(n);
+  std::vector<int32_t> aux(n, -1);
+  std::vector<R> T(n), m(n);
+  // rigid slots ordered by (body, id); moving-wall slots by id
+  std::vector<int64_t> bcount(std::max(P.maxb, 1) + 1, 0);
+  for (int64_t i = 0; i < n; ++i)
+    if (d->kind[i] == SPH_RIGID) bcount[d->body[i] + 1]++;
+  for (int kb = 0; kb < P.maxb; ++kb) bcount[kb + 1] += bcount[kb];
+  std::vector<int64_t> bfill(bcount.begin(), bcount.end() - 1);
+  std::vector<uint32_t> s_id(std::max<int64_t>(P.n_rigid, 1));
+  std::vector<int32_t> s_body(std::max<int64_t>(P.n_rigid, 1)), s_sorted(std::max<int64_t>(P.n_rigid, 1));
+  std::vector<V4<double>> s_x(std::max<int64_t>(P.n_rigid, 1));
+  std::vector<double> s_m(std::max<int64_t>(P.n_rigid, 1));
+  std::vector<V4<double>> w_x0(std::max<int64_t>(P.n_moving, 1)), w_zero(std::max<int64_t>(P.n_moving, 1));
+  std::vector<int32_t> w_sorted(std::max<int64_t>(P.n_moving, 1));
+  int64_t nw = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int kind = d->kind[i];
+    const int ph = d->phase[i];
+    const int moving = (kind == SPH_WALL && d->moving && d->moving[i]) ? 1 : 0;
+    const int body = kind == SPH_RIGID ? d->body[i] : -1;
+    double x[3] = {d->x[3 * i], d->x[3 * i + 1], d->dim == 3 ? d->x[3 * i + 2] : 0.0};
+    // cell of the initial position
+    int c3[3] = {0, 0, 0};
+    for (int ax = 0; ax < P.dim; ++ax) {
+      double vv = std::floor((x[ax] - P.lo[ax]) / P.L);
+      if (!(vv >= 0.0) || vv >= (double)P.nc[ax])
+        return fail(SPH_E_INVALID, "particle " + std::to_string(i) + " outside the cell grid");
+      c3[ax] = (int)vv;
+    }
+    const uint32_t lin = (uint32_t)((int64_t)c3[0] + (int64_t)P.nc[0] * ((int64_t)c3[1] + (int64_t)P.nc[1] * c3[2]));
+    cell[i] = lin;
+    V4<R> o;
+    if (sizeof(R) == 8) {
+      o.x = (R)x[0]; o.y = (R)x[1]; o.z = (R)x[2]; o.w = 0;
+    } else {
+      R off[3] = {0, 0, 0};
+      for (int ax = 0; ax < P.dim; ++ax) {
+        double rel = (x[ax] - P.lo[ax]) - (double)c3[ax] * P.L;
+        float f = (float)rel;
+        off[ax] = f < 0.f ? 0.f : (f > (float)P.L ? (float)P.L : f);
+      }
+      o.x = off[0]; o.y = off[1]; o.z = off[2]; o.w = 0;
+    }
+    pos[i] = o;
+    V4<R> uu;
+    uu.x = (R)d->u[3 * i];
+    uu.y = (R)d->u[3 * i + 1];
+    uu.z = d->dim == 3 ? (R)d->u[3 * i + 2] : (R)0;
+    uu.w = 0;
+    if (moving) uu.x = uu.y = uu.z = 0;
+    u[i] = uu;
+    V4<R> z;
+    z.x = z.y = z.z = z.w = 0;
+    a[i] = z;
+    T[i] = d->T ? (R)d->T[i] : (R)0;
+    // Sec. "Initial particle spacing": mass = reference density x dx^d
+    const double mass = d->mat[ph].rho0 * P.vol0;
+    m[i] = (R)mass;
+    id[i] = (uint32_t)i;
+    info[i] = mkinfo((uint32_t)kind, (uint32_t)ph, (uint32_t)moving, body);
+    if (kind == SPH_RIGID) {
+      const int64_t sl = bfill[body]++;
+      aux[i] = (int32_t)sl;
+      s_id[sl] = (uint32_t)i;
+      s_body[sl] = body;
+      s_sorted[sl] = (int32_t)i;
+      V4<double> xs;
+      xs.x = x[0]; xs.y = x[1]; xs.z = x[2]; xs.w = 0.0;
+      s_x[sl] = xs;
+      s_m[sl] = mass;
+    } else if (moving) {
+      aux[i] = (int32_t)nw;
+      V4<double> xs;
+      xs.x = x[0]; xs.y = x[1]; xs.z = x[2]; xs.w = 0.0;
+      w_x0[nw] = xs;
+      V4<double> zz;
+      zz.x = zz.y = zz.z = zz.w = 0.0;
+      w_zero[nw] = zz;
+      w_sorted[nw] = (int32_t)i;
+      nw++;
+    }
+  }
+  // materials in the sweep precision
+  std::vector<MatT<R>> mats(d->n_mat);
+  for (int k = 0; k < d->n_mat; ++k) {
+    const sph_material& M = d->mat[k];
+    MatT<R>& o = mats[k];
+    o.rho0 = (R)M.rho0;
+    o.p0 = (R)M.p0;
+    o.nu = (R)M.nu;
+    o.cp = (R)M.cp;
+    o.kappa = (R)M.kappa;
+    o.eta = (R)(M.rho0 * M.nu);
+    o.T_t = (R)M.T_t;
+    o.inv_rho0 = (R)(1.0 / M.rho0);
+    o.inv_p0 = (R)(M.p0 != 0.0 ? 1.0 / M.p0 : 0.0);
+    o.inv_cp = (R)(M.cp != 0.0 ? 1.0 / M.cp : 0.0);
+    for (int ax = 0; ax < 3; ++ax) o.b[ax] = (R)(ax < d->dim ? M.b[ax] : 0.0);
+    o.switch_to = M.switch_to;
+    o.dirichlet = M.dirichlet;
+  }
+  // bodies
+  std::vector<Body> bodies(std::max(P.maxb, 1));
+  std::memset(bodies.data(), 0, sizeof(Body) * bodies.size());
+  for (int kb = 0; kb < P.nb; ++kb) {
+    Body& B = bodies[kb];
+    const sph_body_init& I = d->bodies[kb];
+    const double qn = std::sqrt(I.q[0] * I.q[0] + I.q[1] * I.q[1] + I.q[2] * I.q[2] + I.q[3] * I.q[3]);
+    for (int ax = 0; ax < 4; ++ax) B.q[ax] = I.q[ax] / qn;
+    for (int ax = 0; ax < 3; ++ax) {
+      B.u[ax] = ax < d->dim ? I.u[ax] : 0.0;
+      B.w[ax] = (d->dim == 3 || ax == 2) ? I.w[ax] : 0.0;
+    }
+    B.fixed = I.fixed;
+    B.slot0 = (int32_t)bcount[kb];
+    B.nslot = (int32_t)(bcount[kb + 1] - bcount[kb]);
+    B.active = B.nslot > 0;
+    if (B.nslot > 0) {
+      const sph_material& M = d->mat[d->phase[s_id[B.slot0]]];
+      for (int ax = 0; ax < 3; ++ax) B.b[ax] = ax < d->dim ? M.b[ax] : 0.0;
+    }
+  }
+  for (int kb = P.nb; kb < P.maxb; ++kb) {
+    bodies[kb].q[0] = 1.0;
+    bodies[kb].slot0 = (int32_t)P.n_rigid;
+  }
+  // upload into buffer set 0
+  if (n > 0) {
+    HIP_TRY(hipMemcpyAsync(s->pos[0], pos.data(), sizeof(V4<R>) * n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->cell[0], cell.data(), 4 * n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->sb.key, cell.data(), 4 * n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->u[0], u.data(), sizeof(V4<R>) * n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->a[0], a.data(), sizeof(V4<R>) * n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->T[0], T.data(), sizeof(R) * n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->T[1], T.data(), sizeof(R) * n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->m[0], m.data(), sizeof(R) * n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->id[0], id.data(), 4 * n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->info[0], info.data(), 4 * n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->aux[0], aux.data(), 4 * n, hipMemcpyHostToDevice, st));
+  }
+  if (P.n_rigid > 0) {
+    const size_t nr = (size_t)P.n_rigid;
+    HIP_TRY(hipMemcpyAsync(s->s_id, s_id.data(), 4 * nr, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->s_body, s_body.data(), 4 * nr, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->s_sorted, s_sorted.data(), 4 * nr, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->s_x, s_x.data(), sizeof(V4<double>) * nr, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->s_m, s_m.data(), 8 * nr, hipMemcpyHostToDevice, st));
+  }
+  if (P.n_moving > 0) {
+    const size_t nm = (size_t)P.n_moving;
+    HIP_TRY(hipMemcpyAsync(s->w_x0, w_x0.data(), sizeof(V4<double>) * nm, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->w_aw, w_zero.data(), sizeof(V4<double>) * nm, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->w_sorted, w_sorted.data(), 4 * nm, hipMemcpyHostToDevice, st));
+  }
+  HIP_TRY(hipMemcpyAsync(s->bodies, bodies.data(), sizeof(Body) * bodies.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(s->mat, mats.data(), sizeof(MatT<R>) * mats.size(), hipMemcpyHostToDevice, st));
+  launch_fill_u32(s->err, 0u, 4, st);
+  zero_pairs(s, true);
+  s->ip = 0;
+  s->iu = 0;
+  s->iT = 0;
+  // body mass quantities, body-frame offsets, rigid particle velocities
+  if (P.nb > 0) {
+    launch_mass_props_impl(s->bodies, s->s_x, s->s_m, s->s_rb, s->s_rk, P, nullptr, st);
+    Launch<R>::rigid_velocity(cur<R>(s), P, st);
+    launch_rigid_aw(s->bodies, P, s->s_body, s->s_rk, s->s_aw, st);
+  }
+  // first sort, then one evaluation without time update
+  sort_and_permute<R>(s);
+  evaluate<R>(s, 0, 0, 0.0);
+  HIP_TRY(hipStreamSynchronize(st));
+  uint32_t err = 0;
+  HIP_TRY(hipMemcpy(&err, s->err, 4, hipMemcpyDeviceToHost));
+  if (err) return fail(SPH_E_STATE, "device error during set-up: " + std::to_string(err));
+  // the running pair total counts steps only
+  launch_fill_u32(reinterpret_cast<uint32_t*>(s->pairs + 1), 0u, 2, st);
+  HIP_TRY(hipStreamSynchronize(st));
+  return SPH_OK;
+}
+
+size_t arena_for(const sph_scene_desc* d, const Params& P) {
+  sph_scene tmp;
+  std::memset(&tmp, 0, sizeof(tmp));
+  Carver cv{nullptr, 0};
+  if (d->precision == SPH_FP64) carve<double>(cv, &tmp, P, d->n_mat);
+  else carve<float>(cv, &tmp, P, d->n_mat);
+  return align_up(cv.off);
+}
+
+int check_state(sph_scene* s) {
+  if (!s) return fail(SPH_E_INVALID, "null scene");
+  return SPH_OK;
+}
+
+template <typename R>
+int read_particles_impl(sph_scene* s, uint32_t mask, double* out) {
+  const int64_t n = s->P.n;
+  const Params& P = s->P;
+  hipStream_t st = s->stream;
+  HIP_TRY(hipStreamSynchronize(st));
+  std::vector<uint32_t> id(n), cell(n), info(n);
+  std::vector<int32_t> aux(n);
+  std::vector<V4<R>> pos(n), u(n), a(n), uw(n);
+  std::vector<R> rho(n), p(n), T(n), pw(n), m(n), dT(n);
+  std::vector<V4<double>> sf(std::max<int64_t>(P.n_rigid, 1));
+  if (n > 0) {
+    HIP_TRY(hipMemcpy(id.data(), s->id[s->ip], 4 * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(cell.data(), s->cell[s->ip], 4 * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(info.data(), s->info[s->ip], 4 * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(aux.data(), s->aux[s->ip], 4 * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(pos.data(), s->pos[s->ip], sizeof(V4<R>) * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(u.data(), s->u[s->iu], sizeof(V4<R>) * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(a.data(), s->a[s->ip], sizeof(V4<R>) * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(uw.data(), s->uw, sizeof(V4<R>) * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(rho.data(), s->rho, sizeof(R) * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(p.data(), s->p, sizeof(R) * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(T.data(), s->T[s->iT], sizeof(R) * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(pw.data(), s->pw, sizeof(R) * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(m.data(), s->m[s->ip], sizeof(R) * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(dT.data(), s->dTdt, sizeof(R) * n, hipMemcpyDeviceToHost));
+  }
+  if (P.n_rigid > 0)
+    HIP_TRY(hipMemcpy(sf.data(), s->s_f, sizeof(V4<double>) * P.n_rigid, hipMemcpyDeviceToHost));
+  double* o = out;
+  auto vec = [&](auto getter) {
+    for (int64_t i = 0; i < n; ++i) {
+      double v3[3];
+      getter(i, v3);
+      double* dst = &o[3 * (int64_t)id[i]];
+      dst[0] = v3[0];
+      dst[1] = v3[1];
+      dst[2] = P.dim == 3 ? v3[2] : 0.0;
+    }
+    o += 3 * n;
+  };
+  auto sca = [&](auto getter) {
+    for (int64_t i = 0; i < n; ++i) o[id[i]] = getter(i);
+    o += n;
+  };
+  const bool exact = sizeof(R) == 8;
+  if (mask & SPH_F_X) vec([&](int64_t i, double* v3) {
+    const V4<R>& q = pos[i];
+    if (exact) { v3[0] = q.x; v3[1] = q.y; v3[2] = q.z; return; }
+    uint32_t c = cell[i];
+    int cx = (int)(c % (uint32_t)P.nc[0]);
+    int cy = (int)((c / (uint32_t)P.nc[0]) % (uint32_t)P.nc[1]);
+    int cz = (int)(c / ((uint32_t)P.nc[0] * (uint32_t)P.nc[1]));
+    v3[0] = (P.lo[0] + (double)cx * P.L) + (double)q.x;
+    v3[1] = (P.lo[1] + (double)cy * P.L) + (double)q.y;
+    v3[2] = (P.lo[2] + (double)cz * P.L) + (double)q.z;
+  });
+  if (mask & SPH_F_U) vec([&](int64_t i, double* v3) { v3[0] = u[i].x; v3[1] = u[i].y; v3[2] = u[i].z; });
+  if (mask & SPH_F_A) vec([&](int64_t i, double* v3) {
+    bool f = ikind(info[i]) == KF;
+    v3[0] = f ? (double)a[i].x : 0.0; v3[1] = f ? (double)a[i].y : 0.0; v3[2] = f ? (double)a[i].z : 0.0;
+  });
+  if (mask & SPH_F_RHO) sca([&](int64_t i) { return ikind(info[i]) == KW ? 0.0 : (double)rho[i]; });
+  if (mask & SPH_F_P) sca([&](int64_t i) { return ikind(info[i]) == KW ? 0.0 : (double)p[i]; });
+  if (mask & SPH_F_T) sca([&](int64_t i) { return (double)T[i]; });
+  if (mask & SPH_F_PW) sca([&](int64_t i) { return ikind(info[i]) == KF ? 0.0 : (double)pw[i]; });
+  if (mask & SPH_F_UW) vec([&](int64_t i, double* v3) {
+    bool f = ikind(info[i]) == KF;
+    v3[0] = f ? 0.0 : (double)uw[i].x; v3[1] = f ? 0.0 : (double)uw[i].y; v3[2] = f ? 0.0 : (double)uw[i].z;
+  });
+  if (mask & SPH_F_FR) vec([&](int64_t i, double* v3) {
+    if (ikind(info[i]) == KR) { const V4<double>& f = sf[aux[i]]; v3[0] = f.x; v3[1] = f.y; v3[2] = f.z; }
+    else { v3[0] = v3[1] = v3[2] = 0.0; }
+  });
+  if (mask & SPH_F_M) sca([&](int64_t i) { return (double)m[i]; });
+  if (mask & SPH_F_DTDT) sca([&](int64_t i) { return (P.thermal && ikind(info[i]) != KW) ? (double)dT[i] : 0.0; });
+  return SPH_OK;
+}
+
+template <typename R>
+int64_t read_neighbors_impl(sph_scene* s, int64_t* offsets, int32_t* ids, int64_t cap) {
+  const Params& P = s->P;
+  const int64_t n = P.n;
+  hipStream_t st = s->stream;
+  const KC<R> k = make_kc<R>(P);
+  uint32_t* dcnt = nullptr;
+  if (hipMalloc(&dcnt, 4 * std::max<int64_t>(n, 1)) != hipSuccess) { fail(SPH_E_DEVICE, "hipMalloc"); return -1; }
+  Launch<R>::nb_count(cur<R>(s), P, k, dcnt, st);
+  std::vector<uint32_t> cnt(n);
+  if (hipStreamSynchronize(st) != hipSuccess ||
+      (n > 0 && hipMemcpy(cnt.data(), dcnt, 4 * n, hipMemcpyDeviceToHost) != hipSuccess)) {
+    (void)hipFree(dcnt);
+    fail(SPH_E_DEVICE, "neighbour count");
+    return -1;
+  }
+  (void)hipFree(dcnt);
+  std::vector<uint64_t> off(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + cnt[i];
+  const int64_t tot = (int64_t)off[n];
+  if (offsets)
+    for (int64_t i = 0; i <= n; ++i) offsets[i] = (int64_t)off[i];
+  if (!ids || tot > cap) return tot;
+  uint64_t* doff = nullptr;
+  uint32_t* dids = nullptr;
+  if (hipMalloc(&doff, 8 * (n + 1)) != hipSuccess || hipMalloc(&dids, 4 * std::max<int64_t>(tot, 1)) != hipSuccess) {
+    (void)hipFree(doff);
+    fail(SPH_E_DEVICE, "hipMalloc");
+    return -1;
+  }
+  (void)hipMemcpy(doff, off.data(), 8 * (n + 1), hipMemcpyHostToDevice);
+  Launch<R>::nb_fill(cur<R>(s), P, k, doff, dids, st);
+  (void)hipStreamSynchronize(st);
+  std::vector<uint32_t> hids(std::max<int64_t>(tot, 1));
+  if (tot > 0) (void)hipMemcpy(hids.data(), dids, 4 * tot, hipMemcpyDeviceToHost);
+  (void)hipFree(doff);
+  (void)hipFree(dids);
+  for (int64_t i = 0; i < n; ++i) {
+    std::sort(hids.begin() + off[i], hids.begin() + off[i + 1]);
+    for (uint64_t q = off[i]; q < off[i + 1]; ++q) ids[q] = (int32_t)hids[q];
+  }
+  return tot;
+}
+
+void quat_rot(const double* q, double* R) {
+  double w = q[0], x = q[1], y = q[2], z = q[3];
+  R[0] = 1.0 - 2.0 * (y * y + z * z);
+  R[1] = 2.0 * (x * y - w * z);
+  R[2] = 2.0 * (x * z + w * y);
+  R[3] = 2.0 * (x * y + w * z);
+  R[4] = 1.0 - 2.0 * (x * x + z * z);
+  R[5] = 2.0 * (y * z - w * x);
+  R[6] = 2.0 * (x * z - w * y);
+  R[7] = 2.0 * (y * z + w * x);
+  R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+}  // namespace
+
+extern "C" {
+
+int sph_abi_version(void) { return SPH_ABI_VERSION; }
+
+const char* sph_status_string(int status) {
+  switch (status) {
+    case SPH_OK: return "ok";
+    case SPH_E_INVALID: return "invalid argument";
+    case SPH_E_NOMEM: return "arena too small";
+    case SPH_E_DEVICE: return "HIP runtime error";
+    case SPH_E_STATE: return "device error state";
+    case SPH_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* sph_last_error(void) { return g_last_error.c_str(); }
+
+size_t sph_scene_arena_bytes(const sph_scene_desc* d, int* status) {
+  int st = validate(d);
+  Params P;
+  double mmin;
+  if (st == SPH_OK) st = make_params(d, P, &mmin);
+  if (status) *status = st;
+  if (st != SPH_OK) return 0;
+  return arena_for(d, P);
+}
+
+int sph_scene_create(const sph_scene_desc* d, void* dev_arena, size_t arena_bytes, void* hip_stream,
+                     sph_scene** out) {
+  if (!out) return fail(SPH_E_INVALID, "null out");
+  *out = nullptr;
+  int st = validate(d);
+  if (st != SPH_OK) return st;
+  sph_scene* s = new (std::nothrow) sph_scene;
+  if (!s) return fail(SPH_E_NOMEM, "host allocation");
+  std::memset(s, 0, sizeof(*s));
+  double mmin;
+  st = make_params(d, s->P, &mmin);
+  if (st != SPH_OK) { delete s; return st; }
+  const size_t need = arena_for(d, s->P);
+  if (!dev_arena || arena_bytes < need) {
+    delete s;
+    return fail(SPH_E_NOMEM, "arena needs " + std::to_string(need) + " bytes");
+  }
+  if ((reinterpret_cast<uintptr_t>(dev_arena) & 255u) != 0) {
+    delete s;
+    return fail(SPH_E_INVALID, "arena must be 256-byte aligned");
+  }
+  s->precision = d->precision;
+  s->stream = (hipStream_t)hip_stream;
+  s->arena = (char*)dev_arena;
+  s->arena_bytes = arena_bytes;
+  Carver cv{s->arena, 0};
+  if (d->precision == SPH_FP64) carve<double>(cv, s, s->P, d->n_mat);
+  else carve<float>(cv, s, s->P, d->n_mat);
+  Counts c = count(d);
+  s->n_fluid = c.n_fluid;
+  s->n_wall = c.n_wall;
+  st = d->precision == SPH_FP64 ? create_impl<double>(d, s) : create_impl<float>(d, s);
+  if (st != SPH_OK) {
+    (void)hipStreamSynchronize(s->stream);
+    delete s;
+    return st;
+  }
+  *out = s;
+  return SPH_OK;
+}
+
+int sph_scene_step(sph_scene* s, int64_t nsteps) {
+  if (check_state(s)) return SPH_E_INVALID;
+  if (nsteps < 0) return fail(SPH_E_INVALID, "negative step count");
+  for (int64_t k = 0; k < nsteps; ++k) {
+    if (s->precision == SPH_FP64) one_step<double>(s);
+    else one_step<float>(s);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SPH_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+  return SPH_OK;
+}
+
+int sph_batch_step(sph_scene* const* scenes, int32_t n, int64_t nsteps) {
+  if (!scenes || n < 0 || nsteps < 0) return fail(SPH_E_INVALID, "bad batch");
+  for (int64_t k = 0; k < nsteps; ++k)
+    for (int32_t q = 0; q < n; ++q) {
+      sph_scene* s = scenes[q];
+      if (!s) return fail(SPH_E_INVALID, "null scene in batch");
+      if (s->precision == SPH_FP64) one_step<double>(s);
+      else one_step<float>(s);
+    }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SPH_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+  return SPH_OK;
+}
+
+int sph_scene_sync(sph_scene* s) {
+  if (check_state(s)) return SPH_E_INVALID;
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  uint32_t err = 0;
+  HIP_TRY(hipMemcpy(&err, s->err, 4, hipMemcpyDeviceToHost));
+  if (err) return fail(SPH_E_STATE, "device error bits " + std::to_string(err));
+  return SPH_OK;
+}
+
+int sph_scene_read_particles(sph_scene* s, uint32_t field_mask, double* out_host) {
+  if (check_state(s)) return SPH_E_INVALID;
+  if (!out_host) return fail(SPH_E_INVALID, "null output");
+  return s->precision == SPH_FP64 ? read_particles_impl<double>(s, field_mask, out_host)
+                                  : read_particles_impl<float>(s, field_mask, out_host);
+}
+
+int sph_scene_read_bodies(sph_scene* s, double* out_host, int32_t cap, int32_t* n_bodies) {
+  if (check_state(s)) return SPH_E_INVALID;
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  const int nb = s->P.nb;
+  if (n_bodies) *n_bodies = nb;
+  if (!out_host || nb == 0) return SPH_OK;
+  std::vector<Body> b(nb);
+  HIP_TRY(hipMemcpy(b.data(), s->bodies, sizeof(Body) * nb, hipMemcpyDeviceToHost));
+  for (int k = 0; k < std::min(nb, cap); ++k) {
+    double* o = &out_host[SPH_BODY_REC * k];
+    std::memset(o, 0, sizeof(double) * SPH_BODY_REC);
+    const Body& B = b[k];
+    o[0] = B.m;
+    for (int a = 0; a < 3; ++a) {
+      o[1 + a] = B.r[a];
+      o[8 + a] = B.u[a];
+      o[11 + a] = B.w[a];
+      o[14 + a] = B.a[a];
+      o[17 + a] = B.al[a];
+      o[20 + a] = B.f[a];
+      o[23 + a] = B.t[a];
+    }
+    for (int a = 0; a < 4; ++a) o[4 + a] = B.q[a];
+    if (s->P.dim == 3) {
+      double R[9], T[9], I[9];
+      quat_rot(B.q, R);
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          double acc = 0.0;
+          for (int q = 0; q < 3; ++q) acc += R[3 * i + q] * B.Ib[3 * q + j];
+          T[3 * i + j] = acc;
+        }
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          double acc = 0.0;
+          for (int q = 0; q < 3; ++q) acc += T[3 * i + q] * R[3 * j + q];
+          I[3 * i + j] = acc;
+        }
+      o[26] = I[0]; o[27] = I[4]; o[28] = I[8]; o[29] = I[1]; o[30] = I[2]; o[31] = I[5];
+    } else {
+      o[28] = B.Ib[8];
+    }
+    o[32] = B.active;
+    o[33] = B.fixed;
+  }
+  return SPH_OK;
+}
+
+int64_t sph_scene_read_neighbors(sph_scene* s, int64_t* offsets_host, int32_t* ids_host, int64_t cap) {
+  if (check_state(s)) return -1;
+  if (hipStreamSynchronize(s->stream) != hipSuccess) return -1;
+  return s->precision == SPH_FP64 ? read_neighbors_impl<double>(s, offsets_host, ids_host, cap)
+                                  : read_neighbors_impl<float>(s, offsets_host, ids_host, cap);
+}
+
+int sph_scene_read_cell_order(sph_scene* s, int32_t* sorted_ids_host, int32_t* cell_of_id_host) {
+  if (check_state(s)) return SPH_E_INVALID;
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  const int64_t n = s->P.n;
+  std::vector<uint32_t> id(n), cell(n);
+  if (n > 0) {
+    HIP_TRY(hipMemcpy(id.data(), s->id[s->ip], 4 * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(cell.data(), s->cell[s->ip], 4 * n, hipMemcpyDeviceToHost));
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    if (sorted_ids_host) sorted_ids_host[i] = (int32_t)id[i];
+    if (cell_of_id_host) cell_of_id_host[id[i]] = (int32_t)cell[i];
+  }
+  return SPH_OK;
+}
+
+int sph_scene_read_flags(sph_scene* s, int32_t* kind_host, int32_t* phase_host, int32_t* body_host) {
+  if (check_state(s)) return SPH_E_INVALID;
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  const int64_t n = s->P.n;
+  std::vector<uint32_t> id(n), info(n);
+  if (n > 0) {
+    HIP_TRY(hipMemcpy(id.data(), s->id[s->ip], 4 * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(info.data(), s->info[s->ip], 4 * n, hipMemcpyDeviceToHost));
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    if (kind_host) kind_host[id[i]] = (int32_t)ikind(info[i]);
+    if (phase_host) phase_host[id[i]] = (int32_t)iphase(info[i]);
+    if (body_host) body_host[id[i]] = ikind(info[i]) == KR ? ibody(info[i]) : -1;
+  }
+  return SPH_OK;
+}
+
+int sph_scene_read_stats(sph_scene* s, sph_stats* o) {
+  if (check_state(s)) return SPH_E_INVALID;
+  if (!o) return fail(SPH_E_INVALID, "null output");
+  std::memset(o, 0, sizeof(*o));
+  const Params& P = s->P;
+  if (s->precision == SPH_FP64) Launch<double>::global_sums(cur<double>(s), P, s->gpart, kGlobalBlocks, s->gout, s->stream);
+  else Launch<float>::global_sums(cur<float>(s), P, s->gpart, kGlobalBlocks, s->gout, s->stream);
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  unsigned long long pr[2];
+  uint32_t err = 0;
+  double g[5];
+  HIP_TRY(hipMemcpy(pr, s->pairs, sizeof(pr), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(&err, s->err, 4, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(g, s->gout, sizeof(g), hipMemcpyDeviceToHost));
+  o->step = s->step;
+  o->t = (double)s->step * P.dt;
+  o->dt = P.dt;
+  o->k_c = P.kc;
+  o->d_c = P.dc;
+  o->n = P.n;
+  o->n_fluid = s->n_fluid;
+  o->n_wall = s->n_wall;
+  o->n_rigid = P.n_rigid;
+  o->n_bodies = P.nb;
+  for (int a = 0; a < 3; ++a) o->grid[a] = P.nc[a];
+  o->pairs_last = (int64_t)pr[0];
+  o->pairs_total = (int64_t)pr[1];
+  o->device_error = err;
+  // fluid part from the device reduction, bodies added here
+  double mass = g[0], mom[3] = {g[1], g[2], g[3]}, ke = g[4];
+  if (P.nb > 0) {
+    std::vector<Body> b(P.nb);
+    HIP_TRY(hipMemcpy(b.data(), s->bodies, sizeof(Body) * P.nb, hipMemcpyDeviceToHost));
+    for (const Body& B : b) {
+      if (!B.active) continue;
+      mass += B.m;
+      for (int a = 0; a < 3; ++a) mom[a] += B.m * B.u[a];
+      ke += 0.5 * B.m * (B.u[0] * B.u[0] + B.u[1] * B.u[1] + B.u[2] * B.u[2]);
+    }
+  }
+  o->mass = mass;
+  for (int a = 0; a < 3; ++a) o->momentum[a] = mom[a];
+  o->kinetic = ke;
+  return SPH_OK;
+}
+
+int sph_scene_enable_timers(sph_scene* s, int32_t enable) {
+  if (check_state(s)) return SPH_E_INVALID;
+  if (enable && !s->timers) {
+    for (int q = 0; q < 5; ++q) HIP_TRY(hipEventCreate(&s->ev[q]));
+  }
+  s->timers = enable ? 1 : 0;
+  s->t_nb = s->t_sweep = s->t_body = s->t_other = 0.0;
+  return SPH_OK;
+}
+
+int sph_scene_read_timers(sph_scene* s, double* nb, double* sweep, double* body, double* other) {
+  if (check_state(s)) return SPH_E_INVALID;
+  if (nb) *nb = s->t_nb;
+  if (sweep) *sweep = s->t_sweep;
+  if (body) *body = s->t_body;
+  if (other) *other = s->t_other;
+  return SPH_OK;
+}
+
+void sph_scene_destroy(sph_scene* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->stream);
+  if (s->timers || s->ev[0])
+    for (int q = 0; q < 5; ++q)
+      if (s->ev[q]) (void)hipEventDestroy(s->ev[q]);
+  delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,160 @@
+// sph_internal.h -- device data layout and launch interface of the HIP
+// library behind include/sphrb.h (gfx950 only).
+//
+// Particle state lives in device memory sorted by (cell, original id); the
+// fields that a sort permutes are double-buffered.  FP64 mode stores
+// absolute positions; FP32 mode stores the linear cell index plus an FP32
+// offset from the cell's origin, so that every position keeps the same
+// absolute resolution wherever it is in the domain.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace sphrb {
+
+template <typename R>
+struct alignas(16) V4 {
+  R x, y, z, w;
+};
+
+enum : uint32_t { KF = 0, KW = 1, KR = 2 };
+
+// info word: bits 0-1 kind, bit 2 moving wall, bits 8-15 phase, bits 16-31
+// body + 1 (0: none)
+__host__ __device__ inline uint32_t ikind(uint32_t v) { return v & 3u; }
+__host__ __device__ inline bool imoving(uint32_t v) { return ((v >> 2) & 1u) != 0u; }
+__host__ __device__ inline uint32_t iphase(uint32_t v) { return (v >> 8) & 0xffu; }
+__host__ __device__ inline int ibody(uint32_t v) { return (int)(v >> 16) - 1; }
+__host__ __device__ inline uint32_t mkinfo(uint32_t kind, uint32_t phase, uint32_t moving, int body) {
+  return kind | (moving << 2) | (phase << 8) | ((uint32_t)(body + 1) << 16);
+}
+
+enum : uint32_t { ERR_ESCAPE = 1, ERR_CELL = 2, ERR_NONFINITE = 4, ERR_COINCIDENT = 8, ERR_BODYCAP = 16 };
+
+// per-phase constants in the sweep precision
+template <typename R>
+struct MatT {
+  R rho0, p0, nu, cp, kappa, eta, T_t, inv_rho0, inv_p0, inv_cp;
+  R b[3];
+  int32_t switch_to, dirichlet;
+};
+
+// rigid body record (FP64)
+struct Body {
+  double m, r[3], q[4], u[3], w[3], a[3], al[3], f[3], t[3], Ib[9], b[3];
+  int32_t fixed, active, slot0, nslot;
+};
+
+// scalar parameters of one scene
+struct Params {
+  int dim;
+  int nc[3];
+  int64_t ncells;
+  int64_t n;
+  double dx, h, rc, rc2, L, lo[3];
+  double wnorm, dnorm, vol0, Ir_fac;
+  double dt, hdt;
+  double kc, dc;
+  int thermal, contact, pswitch;
+  double wall_A, wall_Om, wall_dir[3];
+  int heat_src;
+  double sQ, ssig, ss0[2], sv[2], sztop, sdepth;
+  int n_mat, nb, maxb;
+  int64_t n_rigid, n_moving;
+};
+
+// constants in the sweep precision
+template <typename R>
+struct KC {
+  R h, inv_h, wnorm, dnorm, rc2, L, dx, dx2, vol0, kc, dc, dt, hdt;
+  R lo[3];
+};
+
+// device pointers of one scene
+template <typename R>
+struct View {
+  // sorted, permuted state (current buffers)
+  V4<R>* pos;
+  uint32_t* cell;
+  V4<R>* u;
+  V4<R>* a;
+  R* T;
+  R* m;
+  uint32_t* id;
+  uint32_t* info;
+  int32_t* aux;
+  // outputs that are swapped in after a sweep
+  V4<R>* u_out;
+  R* T_out;
+  // per-step fields, sorted order
+  R* rho;
+  R* p;
+  R* pw;
+  V4<R>* uw;
+  R* dTdt;
+  // cells
+  uint32_t* cstart;   // C + 1
+  // rigid slots (body-sorted)
+  V4<double>* s_rb;   // body-frame offsets
+  V4<double>* s_rk;   // world-frame offsets R r^b
+  V4<double>* s_f;    // particle forces
+  V4<double>* s_aw;   // particle accelerations as material points
+  V4<double>* s_x;    // FP64 positions (set-up and phase switch)
+  double* s_m;
+  int32_t* s_sorted;
+  int32_t* s_body;
+  uint32_t* s_id;
+  // moving walls
+  V4<double>* w_x0;
+  V4<double>* w_aw;
+  int32_t* w_sorted;
+  // tables
+  const MatT<R>* mat;
+  Body* bodies;
+  // counters
+  uint32_t* err;
+  unsigned long long* pairs;   // [0] last evaluation, [1] running total
+};
+
+struct SortBufs {
+  uint32_t* key;
+  uint32_t* rank;
+  uint32_t* tid;
+  uint32_t* tsrc;
+  uint32_t* perm;
+  uint32_t* ccount;
+  uint32_t* bsum;
+  int64_t nbsum;
+};
+
+// host launchers (one set per precision)
+template <typename R>
+struct Launch {
+  static void kick_drift(const View<R>& v, const Params& P, const KC<R>& k, SortBufs sb, hipStream_t st);
+  static void rigid_pose(const View<R>& v, const Params& P, const KC<R>& k, SortBufs sb, double t, hipStream_t st);
+  static void wall_motion(const View<R>& v, const Params& P, const KC<R>& k, SortBufs sb, double t, hipStream_t st);
+  static void gather(const View<R>& src, const View<R>& dst, const Params& P, SortBufs sb, hipStream_t st);
+  static void density(const View<R>& v, const Params& P, const KC<R>& k, hipStream_t st);
+  static void extrapolate(const View<R>& v, const Params& P, const KC<R>& k, hipStream_t st);
+  static void forces(const View<R>& v, const Params& P, const KC<R>& k, int kick, int heat, double t, hipStream_t st);
+  static void rigid_velocity(const View<R>& v, const Params& P, hipStream_t st);
+  static void global_sums(const View<R>& v, const Params& P, double* partials, int nblocks, double* out, hipStream_t st);
+  static void nb_count(const View<R>& v, const Params& P, const KC<R>& k, uint32_t* cnt, hipStream_t st);
+  static void nb_fill(const View<R>& v, const Params& P, const KC<R>& k, const uint64_t* off, uint32_t* ids, hipStream_t st);
+  static void slot_positions(const View<R>& v, const Params& P, hipStream_t st);
+  static void phase_flags(const View<R>& v, const Params& P, uint32_t* flags, uint32_t* counter, hipStream_t st);
+};
+
+// precision-independent launchers
+void launch_fill_u32(uint32_t* p, uint32_t val, int64_t n, hipStream_t st);
+void launch_sort_keys(const Params& P, SortBufs sb, uint32_t* cstart, const uint32_t* id, hipStream_t st);
+void launch_body_kick_drift(Body* b, const Params& P, hipStream_t st);
+void launch_mass_props_impl(Body* b, const V4<double>* s_x, const double* s_m, V4<double>* s_rb, V4<double>* s_rk,
+                            const Params& P, const uint32_t* only, hipStream_t st);
+void launch_body_reduce(Body* b, const V4<double>* s_f, const V4<double>* s_rk, const Params& P, int kick, hipStream_t st);
+void launch_rigid_aw(Body* b, const Params& P, const int32_t* s_body, const V4<double>* s_rk, V4<double>* s_aw, hipStream_t st);
+
+}  // namespace sphrb

@@ -1,0 +1,1329 @@
+// sph_kernels.hip -- HIP kernels of one SPH time step for gfx950.
+//
+// Every kernel is written for 64-wide wavefronts.  FP64 mode evaluates each
+// expression in the same order as the plain definition written out in the
+// paper's equations (and gathers neighbours in the canonical order: cells
+// dz, dy, dx = -1..1, ascending id inside a cell), so that its sums are
+// reproducible by an independent implementation; it is compiled without
+// floating-point contraction.  FP32 mode uses hardware reciprocal / square
+// root and explicit fused multiply-adds.
+#include "sph_internal.h"
+
+namespace sphrb {
+
+// ---------------------------------------------------------------------------
+// arithmetic helpers
+// ---------------------------------------------------------------------------
+
+template <typename R> struct IsExact { static constexpr bool v = false; };
+template <> struct IsExact<double> { static constexpr bool v = true; };
+
+__device__ __forceinline__ double ksqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float ksqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double kdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ float kdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double kfma(double a, double b, double c) { return a * b + c; }
+__device__ __forceinline__ float kfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+template <typename R> __device__ __forceinline__ R p5(R s) { R t = s * s; t = t * t; return t * s; }
+template <typename R> __device__ __forceinline__ R p4(R s) { R t = s * s; return t * t; }
+
+// quintic spline (Morris 1997), support 3h, normalised in d dimensions
+template <typename R>
+__device__ __forceinline__ R kern_w(R r, const KC<R>& k) {
+  if constexpr (IsExact<R>::v) {
+    R q = r / k.h;
+    if (!(q < R(3))) return R(0);
+    R w = p5(R(3) - q);
+    if (q < R(2)) w = w - R(6) * p5(R(2) - q);
+    if (q < R(1)) w = w + R(15) * p5(R(1) - q);
+    return w * k.wnorm;
+  } else {
+    R q = r * k.inv_h;
+    R s3 = fmaxf(R(3) - q, R(0)), s2 = fmaxf(R(2) - q, R(0)), s1 = fmaxf(R(1) - q, R(0));
+    R w = kfma(R(15), p5(s1), kfma(R(-6), p5(s2), p5(s3)));
+    return w * k.wnorm;
+  }
+}
+template <typename R>
+__device__ __forceinline__ R kern_dw(R r, const KC<R>& k) {
+  if constexpr (IsExact<R>::v) {
+    R q = r / k.h;
+    if (!(q < R(3))) return R(0);
+    R g = p4(R(3) - q);
+    if (q < R(2)) g = g - R(6) * p4(R(2) - q);
+    if (q < R(1)) g = g + R(15) * p4(R(1) - q);
+    return g * k.dnorm;
+  } else {
+    R q = r * k.inv_h;
+    R s3 = fmaxf(R(3) - q, R(0)), s2 = fmaxf(R(2) - q, R(0)), s1 = fmaxf(R(1) - q, R(0));
+    R g = kfma(R(15), p4(s1), kfma(R(-6), p4(s2), p4(s3)));
+    return g * k.dnorm;
+  }
+}
+
+__device__ __forceinline__ void cross3(const double* a, const double* b, double* c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ __forceinline__ void quat_to_rot(const double* q, double* R) {
+  double w = q[0], x = q[1], y = q[2], z = q[3];
+  R[0] = 1.0 - 2.0 * (y * y + z * z);
+  R[1] = 2.0 * (x * y - w * z);
+  R[2] = 2.0 * (x * z + w * y);
+  R[3] = 2.0 * (x * y + w * z);
+  R[4] = 1.0 - 2.0 * (x * x + z * z);
+  R[5] = 2.0 * (y * z - w * x);
+  R[6] = 2.0 * (x * z - w * y);
+  R[7] = 2.0 * (y * z + w * x);
+  R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+__device__ __forceinline__ void mat_vec(const double* R, const double* v, double* o) {
+  o[0] = R[0] * v[0] + R[1] * v[1] + R[2] * v[2];
+  o[1] = R[3] * v[0] + R[4] * v[1] + R[5] * v[2];
+  o[2] = R[6] * v[0] + R[7] * v[1] + R[8] * v[2];
+}
+__device__ __forceinline__ void matT_vec(const double* R, const double* v, double* o) {
+  o[0] = R[0] * v[0] + R[3] * v[1] + R[6] * v[2];
+  o[1] = R[1] * v[0] + R[4] * v[1] + R[7] * v[2];
+  o[2] = R[2] * v[0] + R[5] * v[1] + R[8] * v[2];
+}
+// out = A M A^T with A = R (transpose_first = 0) or R^T (1)
+__device__ __forceinline__ void rot_sandwich(const double* R, const double* M, int tf, double* out) {
+  double A[9], T[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) A[3 * i + j] = tf ? R[3 * j + i] : R[3 * i + j];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s = s + A[3 * i + k] * M[3 * k + j];
+      T[3 * i + j] = s;
+    }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s = s + T[3 * i + k] * A[3 * j + k];
+      out[3 * i + j] = s;
+    }
+}
+
+// error-free two-sum based (double-double) accumulation
+struct DD {
+  double hi, lo;
+};
+__device__ __forceinline__ void dd_add(DD& a, double x) {
+  double s = a.hi + x;
+  double bb = s - a.hi;
+  double e = (a.hi - (s - bb)) + (x - bb);
+  a.hi = s;
+  a.lo = a.lo + e;
+}
+__device__ __forceinline__ DD dd_merge(DD a, DD b) {
+  double s = a.hi + b.hi;
+  double bb = s - a.hi;
+  double e = (a.hi - (s - bb)) + (b.hi - bb);
+  DD r;
+  r.hi = s;
+  r.lo = (a.lo + b.lo) + e;
+  return r;
+}
+
+__device__ __forceinline__ void set_err(uint32_t* err, uint32_t bit) { atomicOr(err, bit); }
+
+// linear cell index of an FP64 position, or -1 outside the grid
+__device__ __forceinline__ long long cell_of(const Params& P, const double* x, int* c3) {
+  long long lin = 0;
+  c3[0] = c3[1] = c3[2] = 0;
+  for (int a = 0; a < P.dim; ++a) {
+    double v = floor((x[a] - P.lo[a]) / P.L);
+    if (!(v >= 0.0) || v >= (double)P.nc[a]) return -1;
+    c3[a] = (int)v;
+  }
+  lin = (long long)c3[0] + (long long)P.nc[0] * ((long long)c3[1] + (long long)P.nc[1] * c3[2]);
+  return lin;
+}
+
+// store an FP64 position into the sweep representation
+template <typename R>
+__device__ __forceinline__ void put_pos(const Params& P, const double* x, V4<R>* pos, uint32_t* cell,
+                                        uint32_t* key, int64_t i, uint32_t* err) {
+  int c3[3];
+  long long lin = cell_of(P, x, c3);
+  if (lin < 0) {
+    set_err(err, ERR_ESCAPE);
+    lin = 0;
+    for (int a = 0; a < P.dim; ++a) {
+      double v = floor((x[a] - P.lo[a]) / P.L);
+      c3[a] = v < 0.0 ? 0 : (v >= P.nc[a] ? P.nc[a] - 1 : (int)v);
+    }
+    lin = (long long)c3[0] + (long long)P.nc[0] * ((long long)c3[1] + (long long)P.nc[1] * c3[2]);
+  }
+  V4<R> o;
+  if constexpr (IsExact<R>::v) {
+    o.x = x[0]; o.y = x[1]; o.z = P.dim == 3 ? x[2] : 0.0; o.w = 0.0;
+  } else {
+    float Lf = (float)P.L;
+    float off[3] = {0.f, 0.f, 0.f};
+    for (int a = 0; a < P.dim; ++a) {
+      double rel = (x[a] - P.lo[a]) - (double)c3[a] * P.L;
+      float f = (float)rel;
+      off[a] = f < 0.f ? 0.f : (f > Lf ? Lf : f);
+    }
+    o.x = off[0]; o.y = off[1]; o.z = off[2]; o.w = 0.f;
+  }
+  pos[i] = o;
+  if (cell) cell[i] = (uint32_t)lin;
+  if (key) key[i] = (uint32_t)lin;
+}
+
+// FP64 position of sorted particle i
+template <typename R>
+__device__ __forceinline__ void get_pos(const Params& P, const View<R>& v, int64_t i, double* x) {
+  V4<R> o = v.pos[i];
+  if constexpr (IsExact<R>::v) {
+    x[0] = o.x; x[1] = o.y; x[2] = o.z;
+  } else {
+    uint32_t c = v.cell[i];
+    int cx = (int)(c % (uint32_t)P.nc[0]);
+    int cy = (int)((c / (uint32_t)P.nc[0]) % (uint32_t)P.nc[1]);
+    int cz = (int)(c / ((uint32_t)P.nc[0] * (uint32_t)P.nc[1]));
+    x[0] = (P.lo[0] + (double)cx * P.L) + (double)o.x;
+    x[1] = (P.lo[1] + (double)cy * P.L) + (double)o.y;
+    x[2] = P.dim == 3 ? (P.lo[2] + (double)cz * P.L) + (double)o.z : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// neighbour gather (canonical order)
+// ---------------------------------------------------------------------------
+
+template <typename R, int DIM, typename F>
+__device__ __forceinline__ void for_neighbors(const View<R>& v, const Params& P, const KC<R>& k, uint32_t i,
+                                              bool with_self, F&& visit) {
+  const uint32_t c = v.cell[i];
+  const int nx = P.nc[0], ny = P.nc[1], nz = P.nc[2];
+  const int cx = (int)(c % (uint32_t)nx);
+  const int cy = (int)((c / (uint32_t)nx) % (uint32_t)ny);
+  const int cz = (int)(c / ((uint32_t)nx * (uint32_t)ny));
+  const V4<R> pi = v.pos[i];
+  constexpr int ZR = DIM == 3 ? 1 : 0;
+  for (int dz = -ZR; dz <= ZR; ++dz) {
+    const int zz = cz + dz;
+    if (zz < 0 || zz >= nz) continue;
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int yy = cy + dy;
+      if (yy < 0 || yy >= ny) continue;
+      const int rowbase = (zz * ny + yy) * nx;
+      for (int ddx = -1; ddx <= 1; ++ddx) {
+        const int xx = cx + ddx;
+        if (xx < 0 || xx >= nx) continue;
+        const int cc = rowbase + xx;
+        const uint32_t j0 = v.cstart[cc], j1 = v.cstart[cc + 1];
+        R tx = pi.x, ty = pi.y, tz = pi.z;
+        if constexpr (!IsExact<R>::v) {
+          tx -= (R)ddx * k.L;
+          ty -= (R)dy * k.L;
+          tz -= (R)dz * k.L;
+        }
+        for (uint32_t j = j0; j < j1; ++j) {
+          if (j == i && !with_self) continue;
+          const V4<R> pj = v.pos[j];
+          const R d0 = tx - pj.x, d1 = ty - pj.y;
+          R d2 = R(0);
+          R r2;
+          if constexpr (IsExact<R>::v) {
+            r2 = d0 * d0 + d1 * d1;
+            if (DIM == 3) { d2 = tz - pj.z; r2 = r2 + d2 * d2; }
+          } else {
+            r2 = kfma(d1, d1, d0 * d0);
+            if (DIM == 3) { d2 = tz - pj.z; r2 = kfma(d2, d2, r2); }
+          }
+          if (r2 < k.rc2) visit(j, d0, d1, d2, r2);
+        }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void block_add_pairs(unsigned long long* pairs, unsigned long long cnt) {
+  // wave-level reduce then one atomic per wave
+  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+  if ((threadIdx.x & 63) == 0 && cnt) {
+    atomicAdd(&pairs[0], cnt);
+    atomicAdd(&pairs[1], cnt);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// density summation and equation of state
+// ---------------------------------------------------------------------------
+
+// eq. nummeth_fluid_densum (self included) and eq. nummeth_fluid_eos
+template <typename R, int DIM>
+__global__ void __launch_bounds__(256) k_density(View<R> v, Params P, KC<R> k) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long cnt = 0;
+  if (i < P.n) {
+    const uint32_t inf = v.info[i];
+    const uint32_t kind = ikind(inf);
+    const MatT<R>& M = v.mat[iphase(inf)];
+    if (kind == KF) {
+      R sum = R(0);
+      uint32_t c = 0;
+      for_neighbors<R, DIM>(v, P, k, (uint32_t)i, true, [&](uint32_t, R, R, R, R r2) {
+        sum = sum + kern_w<R>(ksqrt(r2), k);
+        ++c;
+      });
+      const R rho = v.m[i] * sum;
+      v.rho[i] = rho;
+      if constexpr (IsExact<R>::v) v.p[i] = M.p0 * (rho / M.rho0 - R(1));
+      else v.p[i] = M.p0 * kfma(rho, M.inv_rho0, R(-1));
+      cnt = c - 1;
+    } else if (kind == KR) {
+      v.rho[i] = M.rho0;
+    }
+  }
+  block_add_pairs(v.pairs, cnt);
+}
+
+// ---------------------------------------------------------------------------
+// wall / rigid extrapolation (local force balance, Adami et al. 2012)
+// ---------------------------------------------------------------------------
+
+template <typename R, int DIM>
+__global__ void __launch_bounds__(256) k_extrapolate(View<R> v, Params P, KC<R> k) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long cnt = 0;
+  if (i < P.n) {
+    const uint32_t inf = v.info[i];
+    const uint32_t kind = ikind(inf);
+    if (kind != KF) {
+      R aw[3] = {R(0), R(0), R(0)};
+      if (kind == KR) {
+        const V4<double> a = v.s_aw[v.aux[i]];
+        aw[0] = (R)a.x; aw[1] = (R)a.y; aw[2] = (R)a.z;
+      } else if (imoving(inf)) {
+        const V4<double> a = v.w_aw[v.aux[i]];
+        aw[0] = (R)a.x; aw[1] = (R)a.y; aw[2] = (R)a.z;
+      }
+      R sW = R(0), sp = R(0), su0 = R(0), su1 = R(0), su2 = R(0);
+      uint32_t c = 0;
+      for_neighbors<R, DIM>(v, P, k, (uint32_t)i, false, [&](uint32_t j, R d0, R d1, R d2, R r2) {
+        const uint32_t ij = v.info[j];
+        if (ikind(ij) != KF) return;
+        ++c;
+        const MatT<R>& Mj = v.mat[iphase(ij)];
+        const R W = kern_w<R>(ksqrt(r2), k);
+        R dot;
+        if constexpr (IsExact<R>::v) {
+          dot = (Mj.b[0] - aw[0]) * d0 + (Mj.b[1] - aw[1]) * d1;
+          if (DIM == 3) dot = dot + (Mj.b[2] - aw[2]) * d2;
+        } else {
+          dot = kfma(Mj.b[1] - aw[1], d1, (Mj.b[0] - aw[0]) * d0);
+          if (DIM == 3) dot = kfma(Mj.b[2] - aw[2], d2, dot);
+        }
+        const V4<R> uj = v.u[j];
+        sW = sW + W;
+        if constexpr (IsExact<R>::v) {
+          sp = sp + (v.p[j] + v.rho[j] * dot) * W;
+          su0 = su0 + uj.x * W;
+          su1 = su1 + uj.y * W;
+          if (DIM == 3) su2 = su2 + uj.z * W;
+        } else {
+          sp = kfma(kfma(v.rho[j], dot, v.p[j]), W, sp);
+          su0 = kfma(uj.x, W, su0);
+          su1 = kfma(uj.y, W, su1);
+          if (DIM == 3) su2 = kfma(uj.z, W, su2);
+        }
+      });
+      const V4<R> ui = v.u[i];
+      V4<R> o;
+      o.w = R(0);
+      R pw;
+      if (sW > R(0)) {
+        if constexpr (IsExact<R>::v) {
+          pw = sp / sW;
+          o.x = R(2) * ui.x - su0 / sW;
+          o.y = R(2) * ui.y - su1 / sW;
+          o.z = DIM == 3 ? R(2) * ui.z - su2 / sW : R(0);
+        } else {
+          const R inv = R(1) / sW;
+          pw = sp * inv;
+          o.x = kfma(R(2), ui.x, -su0 * inv);
+          o.y = kfma(R(2), ui.y, -su1 * inv);
+          o.z = DIM == 3 ? kfma(R(2), ui.z, -su2 * inv) : R(0);
+        }
+      } else {
+        pw = R(0);
+        o.x = ui.x; o.y = ui.y; o.z = DIM == 3 ? ui.z : R(0);
+      }
+      v.pw[i] = pw;
+      v.uw[i] = o;
+      if (kind == KR) v.p[i] = pw;
+      cnt = c;
+    }
+  }
+  block_add_pairs(v.pairs, cnt);
+}
+
+// ---------------------------------------------------------------------------
+// momentum, coupling, contact and heat conduction in one gather
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__device__ __forceinline__ R heat_source(const Params& P, double t, const double* x) {
+  if (!P.heat_src) return R(0);
+  const int up = P.dim - 1;
+  if (x[up] < P.sztop - P.sdepth) return R(0);
+  const double c0 = P.ss0[0] + P.sv[0] * t;
+  const double d0 = x[0] - c0;
+  const double ss2 = P.ssig * P.ssig;
+  if (P.dim == 3) {
+    const double c1 = P.ss0[1] + P.sv[1] * t;
+    const double d1 = x[1] - c1;
+    const double dd = d0 * d0 + d1 * d1;
+    return (R)(P.sQ / (2.0 * 3.14159265358979323846 * ss2) * exp(-dd / (2.0 * ss2)));
+  }
+  const double dd = d0 * d0;
+  return (R)(P.sQ / (sqrt(2.0 * 3.14159265358979323846) * P.ssig) * exp(-dd / (2.0 * ss2)));
+}
+
+// Pair force F_ij = m_i a_ij of eq. nummeth_fluid_momentum for fluid "a"
+// against neighbour "b" (d = x_a - x_b); returns the three components.
+template <typename R, int DIM>
+__device__ __forceinline__ void pair_force(R rho_a, R p_a, R m_a, R eta_a, const V4<R>& ua, R rho_b, R p_b,
+                                           R m_b, R eta_b, const V4<R>& ub, R d0, R d1, R d2, R r, R dW,
+                                           R* F) {
+  if constexpr (IsExact<R>::v) {
+    const R Va = m_a / rho_a, Vb = m_b / rho_b;
+    const R vv = Va * Va + Vb * Vb;
+    const R pt = (rho_b * p_a + rho_a * p_b) / (rho_a + rho_b);
+    const R et = (eta_a + eta_b > R(0)) ? (R(2) * eta_a * eta_b) / (eta_a + eta_b) : R(0);
+    const R c = vv * dW / r;
+    F[0] = c * (et * (ua.x - ub.x) - pt * d0);
+    F[1] = c * (et * (ua.y - ub.y) - pt * d1);
+    F[2] = DIM == 3 ? c * (et * (ua.z - ub.z) - pt * d2) : R(0);
+  } else {
+    const R Va = m_a * __builtin_amdgcn_rcpf(rho_a), Vb = m_b * __builtin_amdgcn_rcpf(rho_b);
+    const R vv = kfma(Va, Va, Vb * Vb);
+    const R pt = kfma(rho_b, p_a, rho_a * p_b) * __builtin_amdgcn_rcpf(rho_a + rho_b);
+    const R es = eta_a + eta_b;
+    const R et = es > R(0) ? (R(2) * eta_a * eta_b) * __builtin_amdgcn_rcpf(es) : R(0);
+    const R c = vv * dW * __builtin_amdgcn_rcpf(r);
+    F[0] = c * kfma(et, ua.x - ub.x, -pt * d0);
+    F[1] = c * kfma(et, ua.y - ub.y, -pt * d1);
+    F[2] = DIM == 3 ? c * kfma(et, ua.z - ub.z, -pt * d2) : R(0);
+  }
+}
+
+template <typename R, int DIM, int THERMAL>
+__global__ void __launch_bounds__(256) k_forces(View<R> v, Params P, KC<R> k, int kick, int heat, double t) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.n) return;
+  const uint32_t inf = v.info[i];
+  const uint32_t kind = ikind(inf);
+  const V4<R> ui = v.u[i];
+  const R Ti = v.T[i];
+  if (kind == KW) {
+    v.u_out[i] = ui;
+    if (THERMAL) v.T_out[i] = Ti;
+    return;
+  }
+  const MatT<R>& Mi = v.mat[iphase(inf)];
+  const R m_i = v.m[i];
+  const R rho_i = v.rho[i];
+  const R ka = Mi.kappa;
+  R acc0 = R(0), acc1 = R(0), acc2 = R(0), hs = R(0);
+  bool coincident = false;
+  if (kind == KF) {
+    const R p_i = v.p[i];
+    const R eta_i = Mi.eta;
+    for_neighbors<R, DIM>(v, P, k, (uint32_t)i, false, [&](uint32_t j, R d0, R d1, R d2, R r2) {
+      if (r2 == R(0)) { coincident = true; return; }
+      const uint32_t ij = v.info[j];
+      const uint32_t kj = ikind(ij);
+      const MatT<R>& Mj = v.mat[iphase(ij)];
+      const R r = ksqrt(r2);
+      const R dW = kern_dw<R>(r, k);
+      R F[3];
+      if (kj == KF) {
+        pair_force<R, DIM>(rho_i, p_i, m_i, eta_i, ui, v.rho[j], v.p[j], v.m[j], Mj.eta, v.u[j], d0, d1, d2, r, dW, F);
+      } else {
+        const R p_j = v.pw[j];
+        R rho_j;
+        if constexpr (IsExact<R>::v) rho_j = Mi.rho0 * (p_j / Mi.p0 + R(1));
+        else rho_j = Mi.rho0 * kfma(p_j, Mi.inv_p0, R(1));
+        pair_force<R, DIM>(rho_i, p_i, m_i, eta_i, ui, rho_j, p_j, m_i, eta_i, v.uw[j], d0, d1, d2, r, dW, F);
+      }
+      acc0 = acc0 + F[0];
+      acc1 = acc1 + F[1];
+      if (DIM == 3) acc2 = acc2 + F[2];
+      if (THERMAL) {
+        R Vb;
+        bool th = true;
+        if (kj == KF) Vb = kdiv(v.m[j], v.rho[j]);
+        else if (kj == KR) Vb = kdiv(v.m[j], Mj.rho0);
+        else if (Mj.dirichlet) Vb = k.vol0;
+        else th = false;
+        const R kb = Mj.kappa;
+        if (th && ka + kb > R(0)) {
+          if constexpr (IsExact<R>::v) {
+            const R kk = (R(4) * ka * kb) / (ka + kb);
+            hs = hs + (Vb * kk) * ((Ti - v.T[j]) / r) * dW;
+          } else {
+            const R kk = (R(4) * ka * kb) * __builtin_amdgcn_rcpf(ka + kb);
+            hs = kfma((Vb * kk) * ((Ti - v.T[j]) * __builtin_amdgcn_rcpf(r)), dW, hs);
+          }
+        }
+      }
+    });
+    R a0, a1, a2;
+    if constexpr (IsExact<R>::v) {
+      a0 = acc0 / m_i + Mi.b[0];
+      a1 = acc1 / m_i + Mi.b[1];
+      a2 = DIM == 3 ? acc2 / m_i + Mi.b[2] : R(0);
+    } else {
+      const R im = R(1) / m_i;
+      a0 = kfma(acc0, im, Mi.b[0]);
+      a1 = kfma(acc1, im, Mi.b[1]);
+      a2 = DIM == 3 ? kfma(acc2, im, Mi.b[2]) : R(0);
+    }
+    V4<R> av;
+    av.x = a0; av.y = a1; av.z = a2; av.w = R(0);
+    v.a[i] = av;
+    V4<R> un = ui;
+    if (kick) {
+      un.x = ui.x + k.hdt * a0;
+      un.y = ui.y + k.hdt * a1;
+      if (DIM == 3) un.z = ui.z + k.hdt * a2;
+    }
+    v.u_out[i] = un;
+  } else {
+    // rigid particle: coupling force f_ri = -m_i a_ir, contact
+    const R pw_r = v.pw[i];
+    const V4<R> uw_r = v.uw[i];
+    const int body_i = ibody(inf);
+    for_neighbors<R, DIM>(v, P, k, (uint32_t)i, false, [&](uint32_t j, R d0, R d1, R d2, R r2) {
+      if (r2 == R(0)) { coincident = true; return; }
+      const uint32_t ij = v.info[j];
+      const uint32_t kj = ikind(ij);
+      const MatT<R>& Mj = v.mat[iphase(ij)];
+      const R r = ksqrt(r2);
+      const R dW = kern_dw<R>(r, k);
+      if (kj == KF) {
+        const R rho_a = v.rho[j], p_a = v.p[j], m_a = v.m[j], eta_a = Mj.eta;
+        R rho_b;
+        if constexpr (IsExact<R>::v) rho_b = Mj.rho0 * (pw_r / Mj.p0 + R(1));
+        else rho_b = Mj.rho0 * kfma(pw_r, Mj.inv_p0, R(1));
+        R F[3];
+        pair_force<R, DIM>(rho_a, p_a, m_a, eta_a, v.u[j], rho_b, pw_r, m_a, eta_a, uw_r, -d0, -d1, -d2, r, dW, F);
+        acc0 = acc0 - F[0];
+        acc1 = acc1 - F[1];
+        if (DIM == 3) acc2 = acc2 - F[2];
+      } else if (P.contact && r2 < k.dx2 && (kj == KW || ibody(ij) != body_i)) {
+        const V4<R> uj = v.u[j];
+        R e0, e1, e2 = R(0), en;
+        if constexpr (IsExact<R>::v) {
+          e0 = d0 / r;
+          e1 = d1 / r;
+          en = e0 * (ui.x - uj.x);
+          en = en + e1 * (ui.y - uj.y);
+          if (DIM == 3) { e2 = d2 / r; en = en + e2 * (ui.z - uj.z); }
+        } else {
+          const R ir = __builtin_amdgcn_rcpf(r);
+          e0 = d0 * ir;
+          e1 = d1 * ir;
+          en = kfma(e1, ui.y - uj.y, e0 * (ui.x - uj.x));
+          if (DIM == 3) { e2 = d2 * ir; en = kfma(e2, ui.z - uj.z, en); }
+        }
+        const R fn = k.kc * (r - k.dx) + k.dc * en;
+        if (fn < R(0)) {
+          acc0 = acc0 - fn * e0;
+          acc1 = acc1 - fn * e1;
+          if (DIM == 3) acc2 = acc2 - fn * e2;
+        }
+      }
+      if (THERMAL) {
+        R Vb;
+        bool th = true;
+        if (kj == KF) Vb = kdiv(v.m[j], v.rho[j]);
+        else if (kj == KR) Vb = kdiv(v.m[j], Mj.rho0);
+        else if (Mj.dirichlet) Vb = k.vol0;
+        else th = false;
+        const R kb = Mj.kappa;
+        if (th && ka + kb > R(0)) {
+          if constexpr (IsExact<R>::v) {
+            const R kk = (R(4) * ka * kb) / (ka + kb);
+            hs = hs + (Vb * kk) * ((Ti - v.T[j]) / r) * dW;
+          } else {
+            const R kk = (R(4) * ka * kb) * __builtin_amdgcn_rcpf(ka + kb);
+            hs = kfma((Vb * kk) * ((Ti - v.T[j]) * __builtin_amdgcn_rcpf(r)), dW, hs);
+          }
+        }
+      }
+    });
+    V4<double> f;
+    f.x = (double)acc0; f.y = (double)acc1; f.z = DIM == 3 ? (double)acc2 : 0.0; f.w = 0.0;
+    v.s_f[v.aux[i]] = f;
+    v.u_out[i] = ui;
+  }
+  if (coincident) set_err(v.err, ERR_COINCIDENT);
+  if (THERMAL) {
+    const R rho_a = kind == KF ? rho_i : Mi.rho0;
+    R rate;
+    if constexpr (IsExact<R>::v) rate = hs / (rho_a * Mi.cp);
+    else rate = hs * __builtin_amdgcn_rcpf(rho_a * Mi.cp);
+    if (P.heat_src) {
+      double x[3];
+      get_pos<R>(P, v, i, x);
+      if constexpr (IsExact<R>::v) rate = rate + heat_source<R>(P, t, x) / Mi.cp;
+      else rate = kfma(heat_source<R>(P, t, x), Mi.inv_cp, rate);
+    }
+    v.dTdt[i] = rate;
+    v.T_out[i] = heat ? Ti + k.dt * rate : Ti;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// time integration of particles
+// ---------------------------------------------------------------------------
+
+// first kick and drift of fluid particles, new cell keys of every particle
+template <typename R>
+__global__ void __launch_bounds__(256) k_kick_drift(View<R> v, Params P, KC<R> k, uint32_t* key) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.n) return;
+  const uint32_t inf = v.info[i];
+  uint32_t c = v.cell[i];
+  if (ikind(inf) == KF) {
+    V4<R> u = v.u[i];
+    const V4<R> a = v.a[i];
+    V4<R> x = v.pos[i];
+    u.x = u.x + k.hdt * a.x;
+    u.y = u.y + k.hdt * a.y;
+    if (P.dim == 3) u.z = u.z + k.hdt * a.z;
+    v.u[i] = u;
+    if (!isfinite((double)u.x) || !isfinite((double)u.y) || !isfinite((double)u.z)) set_err(v.err, ERR_NONFINITE);
+    if constexpr (IsExact<R>::v) {
+      x.x = x.x + k.dt * u.x;
+      x.y = x.y + k.dt * u.y;
+      if (P.dim == 3) x.z = x.z + k.dt * u.z;
+      double xx[3] = {x.x, x.y, x.z};
+      int c3[3];
+      long long lin = cell_of(P, xx, c3);
+      if (lin < 0) { set_err(v.err, ERR_ESCAPE); lin = c; }
+      c = (uint32_t)lin;
+    } else {
+      int c3[3];
+      c3[0] = (int)(c % (uint32_t)P.nc[0]);
+      c3[1] = (int)((c / (uint32_t)P.nc[0]) % (uint32_t)P.nc[1]);
+      c3[2] = (int)(c / ((uint32_t)P.nc[0] * (uint32_t)P.nc[1]));
+      R o[3] = {x.x, x.y, x.z};
+      const R uu[3] = {u.x, u.y, u.z};
+      bool esc = false;
+      for (int a = 0; a < P.dim; ++a) {
+        o[a] = kfma(k.dt, uu[a], o[a]);
+        if (o[a] >= k.L) { o[a] -= k.L; c3[a] += 1; }
+        else if (o[a] < R(0)) { o[a] += k.L; c3[a] -= 1; }
+        if (o[a] < R(0)) o[a] = R(0);
+        if (o[a] > k.L) o[a] = k.L;
+        if (c3[a] < 0) { c3[a] = 0; esc = true; }
+        if (c3[a] >= P.nc[a]) { c3[a] = P.nc[a] - 1; esc = true; }
+      }
+      if (esc || !isfinite(o[0]) || !isfinite(o[1]) || !isfinite(o[2])) set_err(v.err, esc ? ERR_ESCAPE : ERR_NONFINITE);
+      x.x = o[0]; x.y = o[1]; x.z = o[2];
+      c = (uint32_t)((long long)c3[0] + (long long)P.nc[0] * ((long long)c3[1] + (long long)P.nc[1] * c3[2]));
+      v.cell[i] = c;
+    }
+    v.pos[i] = x;
+  }
+  key[i] = c;
+}
+
+// rigid particle pose from its body: r_rk = R r^b, x_r = r_k + r_rk,
+// u_r = u_k + w x r_rk, and its acceleration as a material point
+template <typename R>
+__global__ void __launch_bounds__(256) k_rigid_pose(View<R> v, Params P, uint32_t* key) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= P.n_rigid) return;
+  const int kb = v.s_body[s];
+  const Body& B = v.bodies[kb];
+  const int64_t i = v.s_sorted[s];
+  double Rm[9];
+  quat_to_rot(B.q, Rm);
+  const V4<double> rb = v.s_rb[s];
+  const double rbv[3] = {rb.x, rb.y, rb.z};
+  double rk[3], wr[3], t1[3], t3[3];
+  mat_vec(Rm, rbv, rk);
+  if (P.dim == 2) rk[2] = 0.0;
+  cross3(B.w, rk, wr);
+  double x[3];
+  for (int a = 0; a < 3; ++a) x[a] = a < P.dim ? B.r[a] + rk[a] : 0.0;
+  V4<double> rko;
+  rko.x = rk[0]; rko.y = rk[1]; rko.z = rk[2]; rko.w = 0.0;
+  v.s_rk[s] = rko;
+  put_pos<R>(P, x, v.pos, v.cell, key, i, v.err);
+  V4<R> u;
+  u.x = (R)(B.u[0] + wr[0]);
+  u.y = (R)(B.u[1] + wr[1]);
+  u.z = P.dim == 3 ? (R)(B.u[2] + wr[2]) : R(0);
+  u.w = R(0);
+  v.u[i] = u;
+  cross3(B.al, rk, t1);
+  cross3(B.w, wr, t3);
+  V4<double> aw;
+  aw.x = B.a[0] + t1[0] + t3[0];
+  aw.y = B.a[1] + t1[1] + t3[1];
+  aw.z = B.a[2] + t1[2] + t3[2];
+  aw.w = 0.0;
+  v.s_aw[s] = aw;
+}
+
+// moving boundary particles: displacement A (cos(Omega t) - 1) along dir
+template <typename R>
+__global__ void __launch_bounds__(256) k_wall_motion(View<R> v, Params P, uint32_t* key, double t) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= P.n_moving) return;
+  const int64_t i = v.w_sorted[s];
+  const double sA = P.wall_A * (cos(P.wall_Om * t) - 1.0);
+  const double vA = -P.wall_A * P.wall_Om * sin(P.wall_Om * t);
+  const double aA = -P.wall_A * P.wall_Om * P.wall_Om * cos(P.wall_Om * t);
+  const V4<double> x0 = v.w_x0[s];
+  const double xb[3] = {x0.x, x0.y, x0.z};
+  double x[3] = {0.0, 0.0, 0.0};
+  V4<double> aw;
+  aw.x = aw.y = aw.z = aw.w = 0.0;
+  V4<R> u;
+  u.x = u.y = u.z = u.w = R(0);
+  double uu[3] = {0.0, 0.0, 0.0}, aa[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < P.dim; ++a) {
+    x[a] = xb[a] + sA * P.wall_dir[a];
+    uu[a] = vA * P.wall_dir[a];
+    aa[a] = aA * P.wall_dir[a];
+  }
+  u.x = (R)uu[0]; u.y = (R)uu[1]; u.z = (R)uu[2];
+  aw.x = aa[0]; aw.y = aa[1]; aw.z = aa[2];
+  put_pos<R>(P, x, v.pos, v.cell, key, i, v.err);
+  v.u[i] = u;
+  v.w_aw[s] = aw;
+}
+
+// u_r = u_k + w_k x r_rk (second kick of rigid particles)
+template <typename R>
+__global__ void __launch_bounds__(256) k_rigid_velocity(View<R> v, Params P) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= P.n_rigid) return;
+  const Body& B = v.bodies[v.s_body[s]];
+  const V4<double> rk = v.s_rk[s];
+  const double r[3] = {rk.x, rk.y, rk.z};
+  double wr[3];
+  cross3(B.w, r, wr);
+  V4<R> u;
+  u.x = (R)(B.u[0] + wr[0]);
+  u.y = (R)(B.u[1] + wr[1]);
+  u.z = P.dim == 3 ? (R)(B.u[2] + wr[2]) : R(0);
+  u.w = R(0);
+  v.u[v.s_sorted[s]] = u;
+}
+
+// FP64 positions of rigid slots (for the mass quantities)
+template <typename R>
+__global__ void __launch_bounds__(256) k_slot_positions(View<R> v, Params P) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= P.n_rigid) return;
+  const int64_t i = v.s_sorted[s];
+  double x[3];
+  get_pos<R>(P, v, i, x);
+  V4<double> o;
+  o.x = x[0]; o.y = x[1]; o.z = x[2]; o.w = 0.0;
+  v.s_x[s] = o;
+  v.s_m[s] = (double)v.m[i];
+}
+
+// ---------------------------------------------------------------------------
+// counting sort by (cell, id)
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_fill_u32(uint32_t* p, uint32_t val, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = val;
+}
+
+__global__ void __launch_bounds__(256) k_count(const uint32_t* key, uint32_t* count, uint32_t* rank, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) rank[i] = atomicAdd(&count[key[i]], 1u);
+}
+
+// exclusive scan, 1024 elements per block (256 threads x 4)
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* total) {
+  __shared__ uint32_t wsum[4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t inc = x;
+  for (int off = 1; off < 64; off <<= 1) {
+    uint32_t y = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += y;
+  }
+  if (lane == 63) wsum[wid] = inc;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+  for (int w = 0; w < 4; ++w) {
+    if (w < wid) base += wsum[w];
+    tot += wsum[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + inc - x;
+}
+
+__global__ void __launch_bounds__(256) k_scan_blocks(const uint32_t* in, uint32_t* out, uint32_t* bsum, int64_t n) {
+  const int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x * 4;
+  uint32_t v[4], s = 0;
+  for (int q = 0; q < 4; ++q) {
+    v[q] = (base + q < n) ? in[base + q] : 0u;
+    s += v[q];
+  }
+  uint32_t tot;
+  uint32_t ex = block_exclusive_scan(s, &tot);
+  for (int q = 0; q < 4; ++q) {
+    if (base + q < n) out[base + q] = ex;
+    ex += v[q];
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(256) k_scan_bsum(uint32_t* bsum, int64_t nb, uint32_t* out_total) {
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < nb; base += 256) {
+    const int64_t i = base + threadIdx.x;
+    const uint32_t x = i < nb ? bsum[i] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(x, &tot);
+    const uint32_t c = carry;
+    if (i < nb) bsum[i] = ex + c;
+    __syncthreads();
+    if (threadIdx.x == 0) carry = c + tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out_total = carry;
+}
+
+__global__ void __launch_bounds__(256) k_scan_add(uint32_t* out, const uint32_t* bsum, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x * 4;
+  const uint32_t add = bsum[blockIdx.x];
+  for (int q = 0; q < 4; ++q)
+    if (i + q < n) out[i + q] += add;
+}
+
+__global__ void __launch_bounds__(256) k_scatter(const uint32_t* key, const uint32_t* rank, const uint32_t* cstart,
+                                                 const uint32_t* id, uint32_t* tid, uint32_t* tsrc, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t d = cstart[key[i]] + rank[i];
+  tid[d] = id[i];
+  tsrc[d] = (uint32_t)i;
+}
+
+// rank inside the cell by original id -> destination of every source
+constexpr uint32_t kMaxCellSort = 8192;
+__global__ void __launch_bounds__(256) k_rank(const uint32_t* key, const uint32_t* cstart, const uint32_t* tid,
+                                              const uint32_t* tsrc, uint32_t* perm, uint32_t* err, int64_t n) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const uint32_t src = tsrc[p];
+  const uint32_t c = key[src];
+  const uint32_t s0 = cstart[c], s1 = cstart[c + 1];
+  if (s1 - s0 > kMaxCellSort) {
+    set_err(err, ERR_CELL);
+    perm[p] = src;
+    return;
+  }
+  const uint32_t my = tid[p];
+  uint32_t r = 0;
+  for (uint32_t q = s0; q < s1; ++q) r += (tid[q] < my) ? 1u : 0u;
+  perm[s0 + r] = src;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_gather(View<R> a, View<R> b, Params P, const uint32_t* perm,
+                                                const uint32_t* key) {
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= P.n) return;
+  const uint32_t s = perm[d];
+  b.pos[d] = a.pos[s];
+  b.cell[d] = key[s];
+  b.u[d] = a.u[s];
+  b.a[d] = a.a[s];
+  b.T[d] = a.T[s];
+  b.m[d] = a.m[s];
+  b.id[d] = a.id[s];
+  const uint32_t inf = a.info[s];
+  b.info[d] = inf;
+  const int32_t ax = a.aux[s];
+  b.aux[d] = ax;
+  if (ikind(inf) == KR) a.s_sorted[ax] = (int32_t)d;
+  else if (ikind(inf) == KW && imoving(inf)) a.w_sorted[ax] = (int32_t)d;
+}
+
+// ---------------------------------------------------------------------------
+// rigid bodies
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ DD wave_reduce_dd(DD a) {
+  for (int off = 32; off > 0; off >>= 1) {
+    DD b;
+    b.hi = __shfl_xor(a.hi, off, 64);
+    b.lo = __shfl_xor(a.lo, off, 64);
+    a = dd_merge(a, b);
+  }
+  return a;
+}
+
+// block (256 threads) reduction of NV double-double accumulators
+template <int NV>
+__device__ __forceinline__ void block_reduce_dd(DD* acc, double* out) {
+  __shared__ double sh[4][NV][2];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int q = 0; q < NV; ++q) {
+    DD r = wave_reduce_dd(acc[q]);
+    if (lane == 0) { sh[wid][q][0] = r.hi; sh[wid][q][1] = r.lo; }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < NV; ++q) {
+      DD t;
+      t.hi = sh[0][q][0];
+      t.lo = sh[0][q][1];
+      for (int w = 1; w < 4; ++w) {
+        DD b;
+        b.hi = sh[w][q][0];
+        b.lo = sh[w][q][1];
+        t = dd_merge(t, b);
+      }
+      out[q] = t.hi + t.lo;
+    }
+  }
+  __syncthreads();
+}
+
+// body accelerations: a = f/m + b, alpha = (R I^b R^T)^{-1} torque
+__device__ void body_accel(Body& B, int dim) {
+  if (!B.active || B.fixed) {
+    for (int a = 0; a < 3; ++a) { B.a[a] = 0.0; B.al[a] = 0.0; }
+    return;
+  }
+  for (int a = 0; a < 3; ++a) B.a[a] = a < dim ? B.f[a] / B.m + B.b[a] : 0.0;
+  if (dim == 2) {
+    B.al[0] = 0.0;
+    B.al[1] = 0.0;
+    B.al[2] = B.t[2] / B.Ib[8];
+  } else {
+    double Rm[9], I[9];
+    quat_to_rot(B.q, Rm);
+    rot_sandwich(Rm, B.Ib, 0, I);
+    const double c00 = I[4] * I[8] - I[5] * I[7];
+    const double c01 = I[5] * I[6] - I[3] * I[8];
+    const double c02 = I[3] * I[7] - I[4] * I[6];
+    const double det = I[0] * c00 + I[1] * c01 + I[2] * c02;
+    double inv[9];
+    inv[0] = c00 / det;
+    inv[1] = (I[2] * I[7] - I[1] * I[8]) / det;
+    inv[2] = (I[1] * I[5] - I[2] * I[4]) / det;
+    inv[3] = c01 / det;
+    inv[4] = (I[0] * I[8] - I[2] * I[6]) / det;
+    inv[5] = (I[2] * I[3] - I[0] * I[5]) / det;
+    inv[6] = c02 / det;
+    inv[7] = (I[1] * I[6] - I[0] * I[7]) / det;
+    inv[8] = (I[0] * I[4] - I[1] * I[3]) / det;
+    mat_vec(inv, B.t, B.al);
+  }
+}
+
+// Per-body force and torque (eqs. procwise_force, global_force): one
+// workgroup per body; each lane accumulates a strided share of the body's
+// particles in double-double, the wavefront and then the workgroup combine
+// the partial sums; lane 0 forms the accelerations and the second kick.
+__global__ void __launch_bounds__(256) k_body_reduce(Body* bodies, const V4<double>* s_f, const V4<double>* s_rk,
+                                                     int dim, double hdt, int kick) {
+  Body& B = bodies[blockIdx.x];
+  DD acc[6];
+  for (int q = 0; q < 6; ++q) { acc[q].hi = 0.0; acc[q].lo = 0.0; }
+  const int s0 = B.slot0, ns = B.active ? B.nslot : 0;
+  for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+    const V4<double> f = s_f[s0 + q];
+    const V4<double> r = s_rk[s0 + q];
+    const double fv[3] = {f.x, f.y, f.z}, rv[3] = {r.x, r.y, r.z};
+    double t[3];
+    cross3(rv, fv, t);
+    dd_add(acc[0], fv[0]);
+    dd_add(acc[1], fv[1]);
+    dd_add(acc[2], fv[2]);
+    dd_add(acc[3], t[0]);
+    dd_add(acc[4], t[1]);
+    dd_add(acc[5], t[2]);
+  }
+  double out[6];
+  block_reduce_dd<6>(acc, out);
+  if (threadIdx.x == 0) {
+    for (int a = 0; a < 3; ++a) {
+      B.f[a] = a < dim ? out[a] : 0.0;
+      B.t[a] = (dim == 3 || a == 2) ? out[3 + a] : 0.0;
+    }
+    body_accel(B, dim);
+    if (kick && B.active && !B.fixed) {
+      for (int a = 0; a < 3; ++a) {
+        B.u[a] = B.u[a] + hdt * B.a[a];
+        B.w[a] = B.w[a] + hdt * B.al[a];
+      }
+    }
+  }
+}
+
+// first kick, drift and orientation update of every body
+__global__ void __launch_bounds__(64) k_body_kick_drift(Body* bodies, int nb, double dt, double hdt) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nb) return;
+  Body& B = bodies[k];
+  if (!B.active || B.fixed) return;
+  for (int a = 0; a < 3; ++a) {
+    B.u[a] = B.u[a] + hdt * B.a[a];
+    B.w[a] = B.w[a] + hdt * B.al[a];
+  }
+  for (int a = 0; a < 3; ++a) B.r[a] = B.r[a] + dt * B.u[a];
+  const double phi[3] = {dt * B.w[0], dt * B.w[1], dt * B.w[2]};
+  const double ang = sqrt(phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2]);
+  if (ang > 0.0) {
+    const double sh = sin(0.5 * ang) / ang;
+    const double qi[4] = {cos(0.5 * ang), sh * phi[0], sh * phi[1], sh * phi[2]};
+    const double* q = B.q;
+    double qn[4];
+    qn[0] = qi[0] * q[0] - qi[1] * q[1] - qi[2] * q[2] - qi[3] * q[3];
+    qn[1] = qi[0] * q[1] + qi[1] * q[0] + qi[2] * q[3] - qi[3] * q[2];
+    qn[2] = qi[0] * q[2] - qi[1] * q[3] + qi[2] * q[0] + qi[3] * q[1];
+    qn[3] = qi[0] * q[3] + qi[1] * q[2] - qi[2] * q[1] + qi[3] * q[0];
+    const double nq = sqrt(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
+    for (int a = 0; a < 4; ++a) B.q[a] = qn[a] / nq;
+  }
+}
+
+// Mass quantities of every body (eqs. procwise_centerofmass and
+// procwise_inertia): each wavefront of the workgroup forms the partial mass,
+// centre of mass and inertia of its share of particles (a "processor-wise"
+// partial), and the partials are combined with Huygens-Steiner (eqs.
+// global_centerofmass, global_inertia).  Then I^b = R^T I R and the
+// body-frame offsets r^b = R^T (x_r - r_k).
+__global__ void __launch_bounds__(256) k_mass_props(Body* bodies, const V4<double>* s_x, const double* s_m,
+                                                    V4<double>* s_rb, V4<double>* s_rk, int dim, double Ir_fac,
+                                                    const uint32_t* only) {
+  const int kb = blockIdx.x;
+  if (only && !only[kb]) return;
+  Body& B = bodies[kb];
+  const int s0 = B.slot0, ns = B.nslot;
+  __shared__ double shm[4], shr[4][3], shI[4][6];
+  __shared__ double gr[3];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // partition: wavefront w takes slots w, w+4, ... in chunks of 64 lanes
+  DD am, ax[3];
+  am.hi = am.lo = 0.0;
+  for (int a = 0; a < 3; ++a) ax[a].hi = ax[a].lo = 0.0;
+  for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+    const V4<double> x = s_x[s0 + q];
+    const double m = s_m[s0 + q];
+    dd_add(am, m);
+    dd_add(ax[0], m * x.x);
+    dd_add(ax[1], m * x.y);
+    dd_add(ax[2], m * x.z);
+  }
+  DD rm = wave_reduce_dd(am);
+  DD rx[3] = {wave_reduce_dd(ax[0]), wave_reduce_dd(ax[1]), wave_reduce_dd(ax[2])};
+  const double pm = rm.hi + rm.lo;
+  double pr[3];
+  for (int a = 0; a < 3; ++a) pr[a] = pm > 0.0 ? (rx[a].hi + rx[a].lo) / pm : 0.0;
+  // partial inertia about the partial centre of mass
+  DD aI[6];
+  for (int q = 0; q < 6; ++q) aI[q].hi = aI[q].lo = 0.0;
+  for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+    const V4<double> x = s_x[s0 + q];
+    const double m = s_m[s0 + q];
+    const double d[3] = {pr[0] - x.x, pr[1] - x.y, dim == 3 ? pr[2] - x.z : 0.0};
+    const double dsq = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (dim == 2) {
+      dd_add(aI[2], Ir_fac * m + dsq * m);
+    } else {
+      dd_add(aI[0], Ir_fac * m + (dsq - d[0] * d[0]) * m);
+      dd_add(aI[1], Ir_fac * m + (dsq - d[1] * d[1]) * m);
+      dd_add(aI[2], Ir_fac * m + (dsq - d[2] * d[2]) * m);
+      dd_add(aI[3], (-(d[0] * d[1])) * m);
+      dd_add(aI[4], (-(d[0] * d[2])) * m);
+      dd_add(aI[5], (-(d[1] * d[2])) * m);
+    }
+  }
+  double pI[6];
+  for (int q = 0; q < 6; ++q) {
+    DD r = wave_reduce_dd(aI[q]);
+    pI[q] = r.hi + r.lo;
+  }
+  if (lane == 0) {
+    shm[wid] = pm;
+    for (int a = 0; a < 3; ++a) shr[wid][a] = pr[a];
+    for (int q = 0; q < 6; ++q) shI[wid][q] = pI[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    DD M;
+    M.hi = M.lo = 0.0;
+    for (int w = 0; w < 4; ++w) dd_add(M, shm[w]);
+    const double m = M.hi + M.lo;
+    double r[3];
+    for (int a = 0; a < 3; ++a) {
+      DD s;
+      s.hi = s.lo = 0.0;
+      for (int w = 0; w < 4; ++w) dd_add(s, shm[w] * shr[w][a]);
+      r[a] = (a < dim && m > 0.0) ? (s.hi + s.lo) / m : 0.0;
+    }
+    double I6[6];
+    for (int q = 0; q < 6; ++q) {
+      DD s;
+      s.hi = s.lo = 0.0;
+      for (int w = 0; w < 4; ++w) {
+        const double d[3] = {r[0] - shr[w][0], r[1] - shr[w][1], dim == 3 ? r[2] - shr[w][2] : 0.0};
+        const double dsq = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        double st;
+        if (q < 3) st = dsq - d[q] * d[q];
+        else if (q == 3) st = -(d[0] * d[1]);
+        else if (q == 4) st = -(d[0] * d[2]);
+        else st = -(d[1] * d[2]);
+        if (dim == 2 && q != 2) continue;
+        dd_add(s, shI[w][q] + st * shm[w]);
+      }
+      I6[q] = s.hi + s.lo;
+    }
+    B.m = m;
+    for (int a = 0; a < 3; ++a) B.r[a] = r[a];
+    double Iw[9] = {I6[0], I6[3], I6[4], I6[3], I6[1], I6[5], I6[4], I6[5], I6[2]};
+    if (dim == 2) {
+      for (int q = 0; q < 9; ++q) B.Ib[q] = 0.0;
+      B.Ib[8] = I6[2];
+    } else {
+      double Rm[9];
+      quat_to_rot(B.q, Rm);
+      rot_sandwich(Rm, Iw, 1, B.Ib);
+    }
+    B.active = ns > 0 ? 1 : 0;
+    for (int a = 0; a < 3; ++a) gr[a] = r[a];
+  }
+  __syncthreads();
+  double Rm[9];
+  quat_to_rot(B.q, Rm);
+  for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+    const V4<double> x = s_x[s0 + q];
+    double d[3] = {x.x - gr[0], x.y - gr[1], dim == 3 ? x.z - gr[2] : 0.0};
+    double rb[3];
+    matT_vec(Rm, d, rb);
+    if (dim == 2) rb[2] = 0.0;
+    V4<double> o;
+    o.x = d[0]; o.y = d[1]; o.z = d[2]; o.w = 0.0;
+    s_rk[s0 + q] = o;
+    o.x = rb[0]; o.y = rb[1]; o.z = rb[2];
+    s_rb[s0 + q] = o;
+  }
+}
+
+// acceleration of rigid particles as material points (used at set-up)
+__global__ void __launch_bounds__(256) k_rigid_aw(const Body* bodies, const int32_t* s_body, const V4<double>* s_rk,
+                                                  V4<double>* s_aw, int64_t nr) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nr) return;
+  const Body& B = bodies[s_body[s]];
+  const V4<double> r = s_rk[s];
+  const double rk[3] = {r.x, r.y, r.z};
+  double t1[3], t2[3], t3[3];
+  cross3(B.al, rk, t1);
+  cross3(B.w, rk, t2);
+  cross3(B.w, t2, t3);
+  V4<double> o;
+  o.x = B.a[0] + t1[0] + t3[0];
+  o.y = B.a[1] + t1[1] + t3[1];
+  o.z = B.a[2] + t1[2] + t3[2];
+  o.w = 0.0;
+  s_aw[s] = o;
+}
+
+// ---------------------------------------------------------------------------
+// global FP64 checks: mass, momentum, kinetic energy of fluid particles
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_global_partials(View<R> v, Params P, double* part) {
+  DD acc[5];
+  for (int q = 0; q < 5; ++q) acc[q].hi = acc[q].lo = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (ikind(v.info[i]) != KF) continue;
+    const double m = (double)v.m[i];
+    const V4<R> u = v.u[i];
+    const double ux = u.x, uy = u.y, uz = u.z;
+    dd_add(acc[0], m);
+    dd_add(acc[1], m * ux);
+    dd_add(acc[2], m * uy);
+    dd_add(acc[3], m * uz);
+    dd_add(acc[4], 0.5 * m * (ux * ux + uy * uy + uz * uz));
+  }
+  double out[5];
+  block_reduce_dd<5>(acc, out);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 5; ++q) part[5 * blockIdx.x + q] = out[q];
+}
+
+__global__ void __launch_bounds__(256) k_global_final(const double* part, int nb, double* out) {
+  DD acc[5];
+  for (int q = 0; q < 5; ++q) acc[q].hi = acc[q].lo = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x)
+    for (int q = 0; q < 5; ++q) dd_add(acc[q], part[5 * b + q]);
+  double o[5];
+  block_reduce_dd<5>(acc, o);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 5; ++q) out[q] = o[q];
+}
+
+// ---------------------------------------------------------------------------
+// neighbour export (diagnostic)
+// ---------------------------------------------------------------------------
+
+template <typename R, int DIM>
+__global__ void __launch_bounds__(256) k_nb_count(View<R> v, Params P, KC<R> k, uint32_t* cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.n) return;
+  uint32_t c = 0;
+  for_neighbors<R, DIM>(v, P, k, (uint32_t)i, false, [&](uint32_t, R, R, R, R) { ++c; });
+  cnt[v.id[i]] = c;
+}
+
+template <typename R, int DIM>
+__global__ void __launch_bounds__(256) k_nb_fill(View<R> v, Params P, KC<R> k, const uint64_t* off, uint32_t* ids) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.n) return;
+  uint64_t o = off[v.id[i]];
+  for_neighbors<R, DIM>(v, P, k, (uint32_t)i, false, [&](uint32_t j, R, R, R, R) { ids[o++] = v.id[j]; });
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+
+static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+void launch_fill_u32(uint32_t* p, uint32_t val, int64_t n, hipStream_t st) {
+  if (n > 0) k_fill_u32<<<nblk(n), 256, 0, st>>>(p, val, n);
+}
+
+void launch_sort_keys(const Params& P, SortBufs sb, uint32_t* cstart, const uint32_t* id, hipStream_t st) {
+  const int64_t C = P.ncells, n = P.n;
+  launch_fill_u32(sb.ccount, 0u, C, st);
+  if (n > 0) k_count<<<nblk(n), 256, 0, st>>>(sb.key, sb.ccount, sb.rank, n);
+  const int64_t nb = (C + 1023) / 1024;
+  k_scan_blocks<<<(unsigned)nb, 256, 0, st>>>(sb.ccount, cstart, sb.bsum, C);
+  k_scan_bsum<<<1, 256, 0, st>>>(sb.bsum, nb, cstart + C);
+  k_scan_add<<<(unsigned)nb, 256, 0, st>>>(cstart, sb.bsum, C);
+  if (n > 0) {
+    k_scatter<<<nblk(n), 256, 0, st>>>(sb.key, sb.rank, cstart, id, sb.tid, sb.tsrc, n);
+  }
+}
+
+void launch_body_kick_drift(Body* b, const Params& P, hipStream_t st) {
+  if (P.nb > 0) k_body_kick_drift<<<nblk(P.nb, 64), 64, 0, st>>>(b, P.nb, P.dt, P.hdt);
+}
+
+void launch_body_reduce(Body* b, const V4<double>* s_f, const V4<double>* s_rk, const Params& P, int kick,
+                        hipStream_t st) {
+  if (P.nb > 0) k_body_reduce<<<(unsigned)P.nb, 256, 0, st>>>(b, s_f, s_rk, P.dim, P.hdt, kick);
+}
+
+void launch_mass_props_impl(Body* b, const V4<double>* s_x, const double* s_m, V4<double>* s_rb, V4<double>* s_rk,
+                            const Params& P, const uint32_t* only, hipStream_t st) {
+  if (P.nb > 0) k_mass_props<<<(unsigned)P.nb, 256, 0, st>>>(b, s_x, s_m, s_rb, s_rk, P.dim, P.Ir_fac, only);
+}
+
+void launch_rigid_aw(Body* b, const Params& P, const int32_t* s_body, const V4<double>* s_rk, V4<double>* s_aw,
+                     hipStream_t st) {
+  if (P.n_rigid > 0) k_rigid_aw<<<nblk(P.n_rigid), 256, 0, st>>>(b, s_body, s_rk, s_aw, P.n_rigid);
+}
+
+template <typename R>
+void Launch<R>::kick_drift(const View<R>& v, const Params& P, const KC<R>& k, SortBufs sb, hipStream_t st) {
+  if (P.n > 0) k_kick_drift<R><<<nblk(P.n), 256, 0, st>>>(v, P, k, sb.key);
+}
+template <typename R>
+void Launch<R>::rigid_pose(const View<R>& v, const Params& P, const KC<R>&, SortBufs sb, double, hipStream_t st) {
+  if (P.n_rigid > 0) k_rigid_pose<R><<<nblk(P.n_rigid), 256, 0, st>>>(v, P, sb.key);
+}
+template <typename R>
+void Launch<R>::wall_motion(const View<R>& v, const Params& P, const KC<R>&, SortBufs sb, double t, hipStream_t st) {
+  if (P.n_moving > 0) k_wall_motion<R><<<nblk(P.n_moving), 256, 0, st>>>(v, P, sb.key, t);
+}
+template <typename R>
+void Launch<R>::gather(const View<R>& src, const View<R>& dst, const Params& P, SortBufs sb, hipStream_t st) {
+  if (P.n <= 0) return;
+  k_rank<<<nblk(P.n), 256, 0, st>>>(sb.key, src.cstart, sb.tid, sb.tsrc, sb.perm, src.err, P.n);
+  k_gather<R><<<nblk(P.n), 256, 0, st>>>(src, dst, P, sb.perm, sb.key);
+}
+template <typename R>
+void Launch<R>::density(const View<R>& v, const Params& P, const KC<R>& k, hipStream_t st) {
+  if (P.n <= 0) return;
+  if (P.dim == 2) k_density<R, 2><<<nblk(P.n), 256, 0, st>>>(v, P, k);
+  else k_density<R, 3><<<nblk(P.n), 256, 0, st>>>(v, P, k);
+}
+template <typename R>
+void Launch<R>::extrapolate(const View<R>& v, const Params& P, const KC<R>& k, hipStream_t st) {
+  if (P.n <= 0) return;
+  if (P.dim == 2) k_extrapolate<R, 2><<<nblk(P.n), 256, 0, st>>>(v, P, k);
+  else k_extrapolate<R, 3><<<nblk(P.n), 256, 0, st>>>(v, P, k);
+}
+template <typename R>
+void Launch<R>::forces(const View<R>& v, const Params& P, const KC<R>& k, int kick, int heat, double t,
+                       hipStream_t st) {
+  if (P.n <= 0) return;
+  const unsigned g = nblk(P.n);
+  if (P.thermal) {
+    if (P.dim == 2) k_forces<R, 2, 1><<<g, 256, 0, st>>>(v, P, k, kick, heat, t);
+    else k_forces<R, 3, 1><<<g, 256, 0, st>>>(v, P, k, kick, heat, t);
+  } else {
+    if (P.dim == 2) k_forces<R, 2, 0><<<g, 256, 0, st>>>(v, P, k, kick, heat, t);
+    else k_forces<R, 3, 0><<<g, 256, 0, st>>>(v, P, k, kick, heat, t);
+  }
+}
+template <typename R>
+void Launch<R>::rigid_velocity(const View<R>& v, const Params& P, hipStream_t st) {
+  if (P.n_rigid > 0) k_rigid_velocity<R><<<nblk(P.n_rigid), 256, 0, st>>>(v, P);
+}
+template <typename R>
+void Launch<R>::global_sums(const View<R>& v, const Params& P, double* partials, int nblocks, double* out,
+                            hipStream_t st) {
+  k_global_partials<R><<<(unsigned)nblocks, 256, 0, st>>>(v, P, partials);
+  k_global_final<<<1, 256, 0, st>>>(partials, nblocks, out);
+}
+template <typename R>
+void Launch<R>::nb_count(const View<R>& v, const Params& P, const KC<R>& k, uint32_t* cnt, hipStream_t st) {
+  if (P.n <= 0) return;
+  if (P.dim == 2) k_nb_count<R, 2><<<nblk(P.n), 256, 0, st>>>(v, P, k, cnt);
+  else k_nb_count<R, 3><<<nblk(P.n), 256, 0, st>>>(v, P, k, cnt);
+}
+template <typename R>
+void Launch<R>::nb_fill(const View<R>& v, const Params& P, const KC<R>& k, const uint64_t* off, uint32_t* ids,
+                        hipStream_t st) {
+  if (P.n <= 0) return;
+  if (P.dim == 2) k_nb_fill<R, 2><<<nblk(P.n), 256, 0, st>>>(v, P, k, off, ids);
+  else k_nb_fill<R, 3><<<nblk(P.n), 256, 0, st>>>(v, P, k, off, ids);
+}
+template <typename R>
+void Launch<R>::slot_positions(const View<R>& v, const Params& P, hipStream_t st) {
+  if (P.n_rigid > 0) k_slot_positions<R><<<nblk(P.n_rigid), 256, 0, st>>>(v, P);
+}
+template <typename R>
+void Launch<R>::phase_flags(const View<R>&, const Params&, uint32_t*, uint32_t*, hipStream_t) {}
+
+template struct Launch<float>;
+template struct Launch<double>;
+
+}  // namespace sphrb

@@ -1,0 +1,135 @@
+"""GPU (HIP library through the C ABI) against the FP64 oracle.
+
+FP64 mode: neighbour lists, cell order and particle flags bit for bit; every
+field within 1e-10 (field-scaled) after the run.  FP32 mode: the gates fixed
+before measuring -- after one step every field within 1e-5; after the run
+positions and velocities within 1e-3 and densities within 1e-4.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2103_07925_amd import scenes as S
+
+from parity_util import body_errors, field_errors, gpu_fields, oracle_fields, run_pair
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2103_07925_amd import sphrb
+    sphrb.lib()
+    return sphrb
+
+
+def small_3d(seed=0):
+    return S.config_c2(seed=seed, n_side=24, n_per_axis=2, spacing_sites=12, r_range=(2.5, 4.0))
+
+
+def assert_bitwise_structure(o, g, sc):
+    off_o, ids_o = o.neighbors()
+    off_g, ids_g = g.neighbors()
+    assert np.array_equal(off_o, off_g)
+    assert np.array_equal(ids_o, ids_g)
+    so, co = o.cell_order()
+    sg, cg = g.cell_order()
+    assert np.array_equal(co, cg)
+    assert np.array_equal(so, sg)
+    k, ph, b = g.flags()
+    assert np.array_equal(k, o.get_int(O.I_KIND))
+    assert np.array_equal(ph, o.get_int(O.I_PHASE))
+    assert np.array_equal(b, o.get_int(O.I_BODY))
+
+
+@pytest.mark.parametrize("steps", [0, 1, 25])
+def test_c1_fp64_parity(B, steps):
+    sc = S.config_c1(seed=1)
+    o, g = run_pair(sc, B.SPH_FP64, steps)
+    assert_bitwise_structure(o, g, sc)
+    e = field_errors(sc, gpu_fields(g), oracle_fields(o), sc.kind)
+    assert max(e.values()) <= FP64_TOL, e
+    eb = body_errors(sc, g.bodies(), o.bodies())
+    assert max(eb.values()) <= FP64_TOL, eb
+    assert g.stats().pairs_last == o.pair_count
+
+
+def test_c1_fp64_full_run(B):
+    sc = S.config_c1(seed=0)
+    o, g = run_pair(sc, B.SPH_FP64, 1000)
+    assert_bitwise_structure(o, g, sc)
+    e = field_errors(sc, gpu_fields(g), oracle_fields(o), o.get_int(O.I_KIND))
+    assert max(e.values()) <= FP64_TOL, e
+    eb = body_errors(sc, g.bodies(), o.bodies())
+    assert max(eb.values()) <= FP64_TOL, eb
+
+
+@pytest.mark.parametrize("steps", [0, 20])
+def test_3d_bodies_fp64_parity(B, steps):
+    sc = small_3d()
+    o, g = run_pair(sc, B.SPH_FP64, steps)
+    assert_bitwise_structure(o, g, sc)
+    e = field_errors(sc, gpu_fields(g), oracle_fields(o), sc.kind)
+    assert max(e.values()) <= FP64_TOL, e
+    eb = body_errors(sc, g.bodies(), o.bodies())
+    assert max(eb.values()) <= FP64_TOL, eb
+
+
+def test_contact_fp64_parity(B):
+    sc = S.two_particle_bodies(dim=3, dx=0.1, gap=0.05, speed=0.2, k_c=1e4, d_c=0.5)
+    o, g = run_pair(sc, B.SPH_FP64, 8000, dt=2e-5)
+    eb = body_errors(sc, g.bodies(), o.bodies())
+    assert max(eb.values()) <= FP64_TOL, eb
+    assert abs(o.bodies()[0, 8] - 0.2) > 0.1      # the bodies did collide
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_thermal_fp64_parity(B, dim):
+    sc = S.config_c3(seed=2, nsites=(20, 14, 12), n_grains=4 if dim == 3 else 3, median_r=2.5, dim=dim)
+    sc.phase_switch = 0
+    o, g = run_pair(sc, B.SPH_FP64, 20)
+    assert_bitwise_structure(o, g, sc)
+    e = field_errors(sc, gpu_fields(g), oracle_fields(o), sc.kind)
+    assert max(e.values()) <= FP64_TOL, e
+
+
+def test_moving_walls_fp64_parity(B):
+    sc = S.config_c4(seed=3, nsites=(30, 16, 12), n_frag=3, r_range=(1.5, 2.5))
+    o, g = run_pair(sc, B.SPH_FP64, 20)
+    assert_bitwise_structure(o, g, sc)
+    e = field_errors(sc, gpu_fields(g), oracle_fields(o), sc.kind)
+    assert max(e.values()) <= FP64_TOL, e
+
+
+def test_fp64_run_twice_is_bitwise_identical(B):
+    sc = small_3d(seed=4)
+    g1 = B.SphScene(sc, precision=B.SPH_FP64)
+    g2 = B.SphScene(sc, precision=B.SPH_FP64)
+    g1.step(10)
+    g2.step(10)
+    f1, f2 = gpu_fields(g1), gpu_fields(g2)
+    for k in f1:
+        assert np.array_equal(f1[k], f2[k]), k
+    assert np.array_equal(g1.bodies(), g2.bodies())
+
+
+@pytest.mark.parametrize("make", ["c1", "3d"])
+def test_fp32_gates(B, make):
+    sc = S.config_c1(seed=5) if make == "c1" else small_3d(seed=5)
+    o, g = run_pair(sc, B.SPH_FP32_SWEEP, 1)
+    e1 = field_errors(sc, gpu_fields(g), oracle_fields(o), sc.kind)
+    for k in ("x", "u", "rho", "p", "pw", "uw"):
+        assert e1[k] <= 1e-5, (k, e1)
+    n = 200
+    o.step(n - 1)
+    g.step(n - 1)
+    e = field_errors(sc, gpu_fields(g), oracle_fields(o), o.get_int(O.I_KIND))
+    assert e["x"] <= 1e-3 and e["u"] <= 1e-3, e
+    assert e["rho"] <= 1e-4, e
+    eb = body_errors(sc, g.bodies(), o.bodies())
+    assert eb["r"] <= 1e-3 and eb["m"] <= 1e-12, eb
