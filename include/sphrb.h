@@ -120,6 +120,9 @@ typedef struct {
   int32_t n_bodies, grid[3];
   int64_t pairs_last;          /* ordered pairs with a fluid member, last evaluation */
   int64_t pairs_total;         /* summed over all steps taken */
+  int64_t pairs_fluid;         /* last evaluation: neighbours of fluid particles */
+  int64_t pairs_rigid;         /* last evaluation: fluid neighbours of rigid particles */
+  int64_t pairs_wall;          /* last evaluation: fluid neighbours of wall particles */
   uint32_t device_error;       /* SPH_ERR_* bits */
   uint32_t pad;
   double mass, momentum[3], kinetic;   /* FP64 global checks (particles + bodies) */
@@ -187,12 +190,20 @@ int sph_scene_read_flags(sph_scene *s, int32_t *kind_host, int32_t *phase_host, 
 
 int sph_scene_read_stats(sph_scene *s, sph_stats *out_host);
 
-/* Kernel timing: when enabled, every step records HIP events around the
- * neighbour search, the interaction sweep and the per-body reduction and
- * the sums (ms) are returned by sph_scene_read_timers. */
+/* Kernel timing.  When enabled, every step records HIP events on the
+ * scene's stream between its stages, without host synchronisation, for up
+ * to SPH_TIMER_STEPS steps.  sph_scene_read_timers waits for the stream and
+ * returns, summed over the recorded steps, the milliseconds of each stage:
+ * [0] kick/drift and rigid/wall poses, [1] neighbour search (binning and
+ * sort by (cell, id)), [2] density + EOS, [3] wall/rigid extrapolation,
+ * [4] forces + heat, [5] per-body reduction + body integration, [6] rigid
+ * particle velocities.  *steps receives the number of recorded steps and
+ * step_ms (may be NULL) the duration of each recorded step (at most cap).
+ * Enabling again restarts the record. */
+#define SPH_TIMER_STEPS 4096
+#define SPH_TIMER_STAGES 7
 int sph_scene_enable_timers(sph_scene *s, int32_t enable);
-int sph_scene_read_timers(sph_scene *s, double *neighbor_ms, double *sweep_ms, double *body_ms,
-                          double *other_ms);
+int sph_scene_read_timers(sph_scene *s, double *stage_ms, int64_t *steps, double *step_ms, int64_t cap);
 
 /* Release the scene's host-side handle.  Frees nothing the caller owns. */
 void sph_scene_destroy(sph_scene *s);

@@ -99,10 +99,10 @@ struct sph_scene {
   unsigned long long* pairs;
   double* gpart;
   double* gout;
-  // timers
+  // timers: SPH_TIMER_STAGES + 1 events per recorded step
   int timers;
-  hipEvent_t ev[5];
-  double t_nb, t_sweep, t_body, t_other;
+  std::vector<hipEvent_t>* ev;
+  int64_t rec;
 };
 
 namespace {
@@ -244,7 +244,7 @@ void carve(Carver& cv, sph_scene* s, const Params& P, int64_t nmat) {
   s->bodies = cv.take<Body>((size_t)std::max(P.maxb, 1));
   s->mat = cv.take<MatT<R>>((size_t)nmat);
   s->err = cv.take<uint32_t>(4);
-  s->pairs = cv.take<unsigned long long>(2);
+  s->pairs = cv.take<unsigned long long>(6);
   s->gpart = cv.take<double>(5 * kGlobalBlocks);
   s->gout = cv.take<double>(8);
 }
@@ -383,8 +383,12 @@ View<R> cur(sph_scene* s) {
   return make_view<R>(s, s->ip, s->iu, s->iT);
 }
 
+// clear the per-evaluation pair counters (and the running total)
 void zero_pairs(sph_scene* s, bool total) {
-  launch_fill_u32(reinterpret_cast<uint32_t*>(s->pairs), 0u, total ? 4 : 2, s->stream);
+  uint32_t* p = reinterpret_cast<uint32_t*>(s->pairs);
+  launch_fill_u32(p, 0u, 2, s->stream);
+  launch_fill_u32(p + 4, 0u, 6, s->stream);
+  if (total) launch_fill_u32(p + 2, 0u, 2, s->stream);
 }
 
 // counting sort by (cell, id) of the current buffers into the other set
@@ -401,16 +405,19 @@ void sort_and_permute(sph_scene* s) {
 
 // densities, extrapolation, forces (+ heat), body sums
 template <typename R>
-void evaluate(sph_scene* s, int kick, int heat, double t) {
+void evaluate(sph_scene* s, int kick, int heat, double t, hipEvent_t* ev) {
   const KC<R> k = make_kc<R>(s->P);
   View<R> v = cur<R>(s);
   Launch<R>::density(v, s->P, k, s->stream);
+  if (ev) (void)hipEventRecord(ev[3], s->stream);
   Launch<R>::extrapolate(v, s->P, k, s->stream);
+  if (ev) (void)hipEventRecord(ev[4], s->stream);
   Launch<R>::forces(v, s->P, k, kick, heat, t, s->stream);
+  if (ev) (void)hipEventRecord(ev[5], s->stream);
   s->iu = 1 - s->iu;
   if (s->P.thermal) s->iT = 1 - s->iT;
-  if (s->timers) (void)hipEventRecord(s->ev[3], s->stream);
   launch_body_reduce(s->bodies, s->s_f, s->s_rk, s->P, kick, s->stream);
+  if (ev) (void)hipEventRecord(ev[6], s->stream);
 }
 
 template <typename R>
@@ -418,31 +425,24 @@ void one_step(sph_scene* s) {
   const Params& P = s->P;
   const KC<R> k = make_kc<R>(P);
   const double t_new = (double)(s->step + 1) * P.dt;
+  hipEvent_t* ev = nullptr;
+  if (s->timers && s->rec < SPH_TIMER_STEPS) ev = &(*s->ev)[(size_t)s->rec * (SPH_TIMER_STAGES + 1)];
   zero_pairs(s, false);
-  if (s->timers) (void)hipEventRecord(s->ev[0], s->stream);
+  if (ev) (void)hipEventRecord(ev[0], s->stream);
   View<R> v = cur<R>(s);
   Launch<R>::kick_drift(v, P, k, s->sb, s->stream);
   launch_body_kick_drift(s->bodies, P, s->stream);
   Launch<R>::rigid_pose(v, P, k, s->sb, t_new, s->stream);
   Launch<R>::wall_motion(v, P, k, s->sb, t_new, s->stream);
-  if (s->timers) (void)hipEventRecord(s->ev[1], s->stream);
+  if (ev) (void)hipEventRecord(ev[1], s->stream);
   sort_and_permute<R>(s);
-  if (s->timers) (void)hipEventRecord(s->ev[2], s->stream);
-  evaluate<R>(s, 1, 1, t_new);
+  if (ev) (void)hipEventRecord(ev[2], s->stream);
+  evaluate<R>(s, 1, 1, t_new, ev);
   v = cur<R>(s);
   Launch<R>::rigid_velocity(v, P, s->stream);
-  if (s->timers) {
-    (void)hipEventRecord(s->ev[4], s->stream);
-    (void)hipEventSynchronize(s->ev[4]);
-    float a = 0, b = 0, c = 0, d = 0;
-    (void)hipEventElapsedTime(&a, s->ev[0], s->ev[1]);
-    (void)hipEventElapsedTime(&b, s->ev[1], s->ev[2]);
-    (void)hipEventElapsedTime(&c, s->ev[2], s->ev[3]);
-    (void)hipEventElapsedTime(&d, s->ev[3], s->ev[4]);
-    s->t_other += a;
-    s->t_nb += b;
-    s->t_sweep += c;
-    s->t_body += d;
+  if (ev) {
+    (void)hipEventRecord(ev[7], s->stream);
+    s->rec += 1;
   }
   s->step += 1;
 }
@@ -624,7 +624,7 @@ int create_impl(const sph_scene_desc* d, sph_scene* s) {
   }
   // first sort, then one evaluation without time update
   sort_and_permute<R>(s);
-  evaluate<R>(s, 0, 0, 0.0);
+  evaluate<R>(s, 0, 0, 0.0, nullptr);
   HIP_TRY(hipStreamSynchronize(st));
   uint32_t err = 0;
   HIP_TRY(hipMemcpy(&err, s->err, 4, hipMemcpyDeviceToHost));
@@ -994,7 +994,7 @@ int sph_scene_read_stats(sph_scene* s, sph_stats* o) {
   if (s->precision == SPH_FP64) Launch<double>::global_sums(cur<double>(s), P, s->gpart, kGlobalBlocks, s->gout, s->stream);
   else Launch<float>::global_sums(cur<float>(s), P, s->gpart, kGlobalBlocks, s->gout, s->stream);
   HIP_TRY(hipStreamSynchronize(s->stream));
-  unsigned long long pr[2];
+  unsigned long long pr[6];
   uint32_t err = 0;
   double g[5];
   HIP_TRY(hipMemcpy(pr, s->pairs, sizeof(pr), hipMemcpyDeviceToHost));
@@ -1013,6 +1013,9 @@ int sph_scene_read_stats(sph_scene* s, sph_stats* o) {
   for (int a = 0; a < 3; ++a) o->grid[a] = P.nc[a];
   o->pairs_last = (int64_t)pr[0];
   o->pairs_total = (int64_t)pr[1];
+  o->pairs_fluid = (int64_t)pr[2];
+  o->pairs_rigid = (int64_t)pr[3];
+  o->pairs_wall = (int64_t)pr[4];
   o->device_error = err;
   // fluid part from the device reduction, bodies added here
   double mass = g[0], mom[3] = {g[1], g[2], g[3]}, ke = g[4];
@@ -1034,29 +1037,49 @@ int sph_scene_read_stats(sph_scene* s, sph_stats* o) {
 
 int sph_scene_enable_timers(sph_scene* s, int32_t enable) {
   if (check_state(s)) return SPH_E_INVALID;
-  if (enable && !s->timers) {
-    for (int q = 0; q < 5; ++q) HIP_TRY(hipEventCreate(&s->ev[q]));
+  if (enable && !s->ev) {
+    s->ev = new (std::nothrow) std::vector<hipEvent_t>((size_t)SPH_TIMER_STEPS * (SPH_TIMER_STAGES + 1), nullptr);
+    if (!s->ev) return fail(SPH_E_NOMEM, "host allocation");
+    for (hipEvent_t& e : *s->ev) HIP_TRY(hipEventCreate(&e));
   }
   s->timers = enable ? 1 : 0;
-  s->t_nb = s->t_sweep = s->t_body = s->t_other = 0.0;
+  s->rec = 0;
   return SPH_OK;
 }
 
-int sph_scene_read_timers(sph_scene* s, double* nb, double* sweep, double* body, double* other) {
+int sph_scene_read_timers(sph_scene* s, double* stage_ms, int64_t* steps, double* step_ms, int64_t cap) {
   if (check_state(s)) return SPH_E_INVALID;
-  if (nb) *nb = s->t_nb;
-  if (sweep) *sweep = s->t_sweep;
-  if (body) *body = s->t_body;
-  if (other) *other = s->t_other;
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  double sum[SPH_TIMER_STAGES] = {0.0};
+  const int64_t nrec = s->ev ? s->rec : 0;
+  for (int64_t q = 0; q < nrec; ++q) {
+    hipEvent_t* e = &(*s->ev)[(size_t)q * (SPH_TIMER_STAGES + 1)];
+    static const int from[SPH_TIMER_STAGES] = {0, 1, 2, 3, 4, 5, 6};
+    for (int g = 0; g < SPH_TIMER_STAGES; ++g) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e[from[g]], e[from[g] + 1]));
+      sum[g] += ms;
+    }
+    if (step_ms && q < cap) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e[0], e[SPH_TIMER_STAGES]));
+      step_ms[q] = ms;
+    }
+  }
+  if (stage_ms)
+    for (int g = 0; g < SPH_TIMER_STAGES; ++g) stage_ms[g] = sum[g];
+  if (steps) *steps = nrec;
   return SPH_OK;
 }
 
 void sph_scene_destroy(sph_scene* s) {
   if (!s) return;
   (void)hipStreamSynchronize(s->stream);
-  if (s->timers || s->ev[0])
-    for (int q = 0; q < 5; ++q)
-      if (s->ev[q]) (void)hipEventDestroy(s->ev[q]);
+  if (s->ev) {
+    for (hipEvent_t e : *s->ev)
+      if (e) (void)hipEventDestroy(e);
+    delete s->ev;
+  }
   delete s;
 }
 

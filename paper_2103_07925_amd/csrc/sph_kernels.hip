@@ -246,12 +246,14 @@ __device__ __forceinline__ void for_neighbors(const View<R>& v, const Params& P,
   }
 }
 
-__device__ __forceinline__ void block_add_pairs(unsigned long long* pairs, unsigned long long cnt) {
-  // wave-level reduce then one atomic per wave
+// pair counters: [0] last evaluation, [1] running total, [2] fluid targets,
+// [3] fluid neighbours of rigid targets, [4] fluid neighbours of walls
+__device__ __forceinline__ void block_add_pairs(unsigned long long* pairs, unsigned long long cnt, int slot) {
   for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
   if ((threadIdx.x & 63) == 0 && cnt) {
     atomicAdd(&pairs[0], cnt);
     atomicAdd(&pairs[1], cnt);
+    atomicAdd(&pairs[slot], cnt);
   }
 }
 
@@ -284,7 +286,7 @@ __global__ void __launch_bounds__(256) k_density(View<R> v, Params P, KC<R> k) {
       v.rho[i] = M.rho0;
     }
   }
-  block_add_pairs(v.pairs, cnt);
+  block_add_pairs(v.pairs, cnt, 2);
 }
 
 // ---------------------------------------------------------------------------
@@ -294,7 +296,7 @@ __global__ void __launch_bounds__(256) k_density(View<R> v, Params P, KC<R> k) {
 template <typename R, int DIM>
 __global__ void __launch_bounds__(256) k_extrapolate(View<R> v, Params P, KC<R> k) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long cnt = 0;
+  unsigned long long cnt_r = 0, cnt_w = 0;
   if (i < P.n) {
     const uint32_t inf = v.info[i];
     const uint32_t kind = ikind(inf);
@@ -361,10 +363,12 @@ __global__ void __launch_bounds__(256) k_extrapolate(View<R> v, Params P, KC<R> 
       v.pw[i] = pw;
       v.uw[i] = o;
       if (kind == KR) v.p[i] = pw;
-      cnt = c;
+      if (kind == KR) cnt_r = c;
+      else cnt_w = c;
     }
   }
-  block_add_pairs(v.pairs, cnt);
+  block_add_pairs(v.pairs, cnt_r, 3);
+  block_add_pairs(v.pairs, cnt_w, 4);
 }
 
 // ---------------------------------------------------------------------------

@@ -62,7 +62,8 @@ class sph_stats(C.Structure):
     _fields_ = [("step", C.c_int64), ("t", C.c_double), ("dt", C.c_double), ("k_c", C.c_double),
                 ("d_c", C.c_double), ("n", C.c_int64), ("n_fluid", C.c_int64), ("n_wall", C.c_int64),
                 ("n_rigid", C.c_int64), ("n_bodies", C.c_int32), ("grid", C.c_int32 * 3),
-                ("pairs_last", C.c_int64), ("pairs_total", C.c_int64), ("device_error", C.c_uint32),
+                ("pairs_last", C.c_int64), ("pairs_total", C.c_int64), ("pairs_fluid", C.c_int64),
+                ("pairs_rigid", C.c_int64), ("pairs_wall", C.c_int64), ("device_error", C.c_uint32),
                 ("pad", C.c_uint32), ("mass", C.c_double), ("momentum", C.c_double * 3),
                 ("kinetic", C.c_double)]
 
@@ -103,7 +104,7 @@ def lib():
     L.sph_scene_read_flags.argtypes = [C.c_void_p, _ip, _ip, _ip]
     L.sph_scene_read_stats.argtypes = [C.c_void_p, C.POINTER(sph_stats)]
     L.sph_scene_enable_timers.argtypes = [C.c_void_p, C.c_int32]
-    L.sph_scene_read_timers.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
+    L.sph_scene_read_timers.argtypes = [C.c_void_p, _dp, C.POINTER(C.c_int64), _dp, C.c_int64]
     L.sph_scene_destroy.argtypes = [C.c_void_p]
     L.sph_scene_destroy.restype = None
     _lib = L
@@ -319,10 +320,21 @@ class SphScene:
     def sph_scene_enable_timers(self, enable=True):
         _check(lib().sph_scene_enable_timers(self.handle, int(enable)), "sph_scene_enable_timers")
 
-    def sph_scene_read_timers(self):
-        v = [C.c_double(0.0) for _ in range(4)]
-        _check(lib().sph_scene_read_timers(self.handle, *[C.byref(x) for x in v]), "sph_scene_read_timers")
-        return {"neighbor_ms": v[0].value, "sweep_ms": v[1].value, "body_ms": v[2].value, "other_ms": v[3].value}
+    STAGES = ["integrate", "neighbor_search", "density", "extrapolate", "forces", "body_reduce", "rigid_velocity"]
+
+    def sph_scene_read_timers(self, with_steps=False):
+        """Per-stage milliseconds summed over the recorded steps, the number
+        of recorded steps and (optionally) each step's duration."""
+        ms = np.zeros(7, np.float64)
+        nrec = C.c_int64(0)
+        steps = np.zeros(4096, np.float64)
+        _check(lib().sph_scene_read_timers(self.handle, _d(ms), C.byref(nrec), _d(steps), 4096),
+               "sph_scene_read_timers")
+        out = {k: float(v) for k, v in zip(self.STAGES, ms)}
+        out["steps"] = int(nrec.value)
+        if with_steps:
+            out["step_ms"] = steps[:nrec.value].copy()
+        return out
 
 
 def sph_batch_step(scenes, nsteps=1):
