@@ -56,7 +56,8 @@ enum {
   SPH_ERR_CELL = 2,        /* a cell holds more particles than the sort supports */
   SPH_ERR_NONFINITE = 4,   /* non-finite position or velocity */
   SPH_ERR_COINCIDENT = 8,  /* two distinct particles at distance zero */
-  SPH_ERR_BODYCAP = 16     /* solidification needs more bodies than max_bodies */
+  SPH_ERR_BODYCAP = 16,    /* solidification needs more bodies than max_bodies */
+  SPH_ERR_NBCAP = 32       /* a particle has more neighbours than the list capacity */
 };
 
 /* One phase (material).  p0 is the reference pressure of the equation of

@@ -84,7 +84,7 @@ struct sph_scene {
   uint32_t* info[2];
   int32_t* aux[2];
   int ip, iu, iT;
-  void *rho, *p, *pw, *uw, *dTdt;
+  void *rho, *p, *pw, *uw, *dTdt, *vp, *rm;
   SortBufs sb;
   uint32_t* cstart;
   V4<double> *s_rb, *s_rk, *s_f, *s_aw, *s_x;
@@ -97,6 +97,8 @@ struct sph_scene {
   void* mat;
   uint32_t* err;
   unsigned long long* pairs;
+  Lists nb;
+  uint32_t *wcount, *woff, *wbsum;
   double* gpart;
   double* gout;
   // timers: SPH_TIMER_STAGES + 1 events per recorded step
@@ -219,6 +221,8 @@ void carve(Carver& cv, sph_scene* s, const Params& P, int64_t nmat) {
   s->pw = cv.take<R>(n);
   s->uw = cv.take<V4<R>>(n);
   s->dTdt = cv.take<R>(n);
+  s->vp = cv.take<V4<R>>(n);
+  s->rm = cv.take<V4<R>>(n);
   s->sb.key = cv.take<uint32_t>(n);
   s->sb.rank = cv.take<uint32_t>(n);
   s->sb.tid = cv.take<uint32_t>(n);
@@ -245,6 +249,16 @@ void carve(Carver& cv, sph_scene* s, const Params& P, int64_t nmat) {
   s->mat = cv.take<MatT<R>>((size_t)nmat);
   s->err = cv.take<uint32_t>(4);
   s->pairs = cv.take<unsigned long long>(6);
+  // compact neighbour lists: one slot per possible wave
+  const int cap = P.dim == 3 ? 160 : 48, nsr = P.dim == 3 ? 9 : 3;
+  s->nb.table = cv.take<WaveInfo>((size_t)P.max_waves);
+  s->nb.ent = cv.take<uint16_t>((size_t)P.max_waves * cap * 64);
+  s->nb.cnt = cv.take<uint16_t>((size_t)P.max_waves * 64);
+  s->nb.jlo = cv.take<uint32_t>((size_t)P.max_waves * nsr);
+  s->wcount = cv.take<uint32_t>((size_t)P.nrows);
+  s->woff = cv.take<uint32_t>((size_t)P.nrows + 1);
+  s->wbsum = cv.take<uint32_t>((size_t)(P.nrows + 1023) / 1024 + 1);
+  s->nb.nwaves = s->woff + P.nrows;
   s->gpart = cv.take<double>(5 * kGlobalBlocks);
   s->gout = cv.take<double>(8);
 }
@@ -315,6 +329,8 @@ int make_params(const sph_scene_desc* d, Params& P, double* m_min) {
   Counts c = count(d);
   P.n_rigid = c.n_rigid;
   P.n_moving = c.n_moving;
+  P.nrows = (int64_t)P.nc[1] * P.nc[2];
+  P.max_waves = (P.n + 63) / 64 + P.nrows + 1;
   *m_min = mmin;
   return SPH_OK;
 }
@@ -358,6 +374,8 @@ View<R> make_view(sph_scene* s, int ip, int iu, int iT) {
   v.pw = (R*)s->pw;
   v.uw = (V4<R>*)s->uw;
   v.dTdt = (R*)s->dTdt;
+  v.vp = (V4<R>*)s->vp;
+  v.rm = (V4<R>*)s->rm;
   v.cstart = s->cstart;
   v.s_rb = s->s_rb;
   v.s_rk = s->s_rk;
@@ -375,6 +393,7 @@ View<R> make_view(sph_scene* s, int ip, int iu, int iT) {
   v.bodies = s->bodies;
   v.err = s->err;
   v.pairs = s->pairs;
+  v.nb = s->nb;
   return v;
 }
 
@@ -398,6 +417,7 @@ void sort_and_permute(sph_scene* s) {
   launch_sort_keys(s->P, s->sb, s->cstart, src.id, s->stream);
   View<R> dst = make_view<R>(s, 1 - s->ip, 1 - s->iu, 1 - s->iT);
   Launch<R>::gather(src, dst, s->P, s->sb, s->stream);
+  launch_wave_table(s->P, s->cstart, s->wcount, s->woff, s->wbsum, s->nb.table, s->stream);
   s->ip = 1 - s->ip;
   s->iu = 1 - s->iu;
   s->iT = 1 - s->iT;
@@ -496,7 +516,7 @@ int create_impl(const sph_scene_desc* d, sph_scene* s) {
         float f = (float)rel;
         off[ax] = f < 0.f ? 0.f : (f > (float)P.L ? (float)P.L : f);
       }
-      o.x = off[0]; o.y = off[1]; o.z = off[2]; o.w = 0;
+      o.x = off[0]; o.y = off[1]; o.z = off[2]; o.w = (R)c3[0];
     }
     pos[i] = o;
     V4<R> uu;

@@ -32,7 +32,7 @@ __host__ __device__ inline uint32_t mkinfo(uint32_t kind, uint32_t phase, uint32
   return kind | (moving << 2) | (phase << 8) | ((uint32_t)(body + 1) << 16);
 }
 
-enum : uint32_t { ERR_ESCAPE = 1, ERR_CELL = 2, ERR_NONFINITE = 4, ERR_COINCIDENT = 8, ERR_BODYCAP = 16 };
+enum : uint32_t { ERR_ESCAPE = 1, ERR_CELL = 2, ERR_NONFINITE = 4, ERR_COINCIDENT = 8, ERR_BODYCAP = 16, ERR_NBCAP = 32 };
 
 // per-phase constants in the sweep precision
 template <typename R>
@@ -64,6 +64,23 @@ struct Params {
   double sQ, ssig, ss0[2], sv[2], sztop, sdepth;
   int n_mat, nb, maxb;
   int64_t n_rigid, n_moving;
+  int64_t nrows, max_waves;
+};
+
+// one wavefront of the sweeps: up to 64 consecutive sorted particles of one
+// x-row of cells
+struct WaveInfo {
+  uint32_t p0, cnt, row, pad;
+};
+
+// compact neighbour lists, [wave][entry][lane] (16-bit entries), per-lane
+// counts and per-wave first candidate index of every stencil row
+struct Lists {
+  WaveInfo* table;
+  uint32_t* nwaves;
+  uint16_t* ent;
+  uint16_t* cnt;
+  uint32_t* jlo;
 };
 
 // constants in the sweep precision
@@ -95,6 +112,8 @@ struct View {
   R* pw;
   V4<R>* uw;
   R* dTdt;
+  V4<R>* vp;   // neighbour record: (u, p) of fluid, (u~_w, p_w) of wall / rigid particles
+  V4<R>* rm;   // neighbour record: (rho, m, info bits, T)
   // cells
   uint32_t* cstart;   // C + 1
   // rigid slots (body-sorted)
@@ -116,7 +135,8 @@ struct View {
   Body* bodies;
   // counters
   uint32_t* err;
-  unsigned long long* pairs;   // [0] last evaluation, [1] running total
+  unsigned long long* pairs;   // [0] last evaluation, [1] running total, [2..4] by target kind
+  Lists nb;
 };
 
 struct SortBufs {
@@ -150,6 +170,9 @@ struct Launch {
 
 // precision-independent launchers
 void launch_fill_u32(uint32_t* p, uint32_t val, int64_t n, hipStream_t st);
+void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum, hipStream_t st);
+void launch_wave_table(const Params& P, const uint32_t* cstart, uint32_t* wcount, uint32_t* woff, uint32_t* bsum,
+                       WaveInfo* table, hipStream_t st);
 void launch_sort_keys(const Params& P, SortBufs sb, uint32_t* cstart, const uint32_t* id, hipStream_t st);
 void launch_body_kick_drift(Body* b, const Params& P, hipStream_t st);
 void launch_mass_props_impl(Body* b, const V4<double>* s_x, const double* s_m, V4<double>* s_rb, V4<double>* s_rk,

@@ -170,7 +170,7 @@ __device__ __forceinline__ void put_pos(const Params& P, const double* x, V4<R>*
       float f = (float)rel;
       off[a] = f < 0.f ? 0.f : (f > Lf ? Lf : f);
     }
-    o.x = off[0]; o.y = off[1]; o.z = off[2]; o.w = 0.f;
+    o.x = off[0]; o.y = off[1]; o.z = off[2]; o.w = (float)c3[0];
   }
   pos[i] = o;
   if (cell) cell[i] = (uint32_t)lin;
@@ -194,58 +194,6 @@ __device__ __forceinline__ void get_pos(const Params& P, const View<R>& v, int64
   }
 }
 
-// ---------------------------------------------------------------------------
-// neighbour gather (canonical order)
-// ---------------------------------------------------------------------------
-
-template <typename R, int DIM, typename F>
-__device__ __forceinline__ void for_neighbors(const View<R>& v, const Params& P, const KC<R>& k, uint32_t i,
-                                              bool with_self, F&& visit) {
-  const uint32_t c = v.cell[i];
-  const int nx = P.nc[0], ny = P.nc[1], nz = P.nc[2];
-  const int cx = (int)(c % (uint32_t)nx);
-  const int cy = (int)((c / (uint32_t)nx) % (uint32_t)ny);
-  const int cz = (int)(c / ((uint32_t)nx * (uint32_t)ny));
-  const V4<R> pi = v.pos[i];
-  constexpr int ZR = DIM == 3 ? 1 : 0;
-  for (int dz = -ZR; dz <= ZR; ++dz) {
-    const int zz = cz + dz;
-    if (zz < 0 || zz >= nz) continue;
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int yy = cy + dy;
-      if (yy < 0 || yy >= ny) continue;
-      const int rowbase = (zz * ny + yy) * nx;
-      for (int ddx = -1; ddx <= 1; ++ddx) {
-        const int xx = cx + ddx;
-        if (xx < 0 || xx >= nx) continue;
-        const int cc = rowbase + xx;
-        const uint32_t j0 = v.cstart[cc], j1 = v.cstart[cc + 1];
-        R tx = pi.x, ty = pi.y, tz = pi.z;
-        if constexpr (!IsExact<R>::v) {
-          tx -= (R)ddx * k.L;
-          ty -= (R)dy * k.L;
-          tz -= (R)dz * k.L;
-        }
-        for (uint32_t j = j0; j < j1; ++j) {
-          if (j == i && !with_self) continue;
-          const V4<R> pj = v.pos[j];
-          const R d0 = tx - pj.x, d1 = ty - pj.y;
-          R d2 = R(0);
-          R r2;
-          if constexpr (IsExact<R>::v) {
-            r2 = d0 * d0 + d1 * d1;
-            if (DIM == 3) { d2 = tz - pj.z; r2 = r2 + d2 * d2; }
-          } else {
-            r2 = kfma(d1, d1, d0 * d0);
-            if (DIM == 3) { d2 = tz - pj.z; r2 = kfma(d2, d2, r2); }
-          }
-          if (r2 < k.rc2) visit(j, d0, d1, d2, r2);
-        }
-      }
-    }
-  }
-}
-
 // pair counters: [0] last evaluation, [1] running total, [2] fluid targets,
 // [3] fluid neighbours of rigid targets, [4] fluid neighbours of walls
 __device__ __forceinline__ void block_add_pairs(unsigned long long* pairs, unsigned long long cnt, int slot) {
@@ -258,122 +206,97 @@ __device__ __forceinline__ void block_add_pairs(unsigned long long* pairs, unsig
 }
 
 // ---------------------------------------------------------------------------
-// density summation and equation of state
+// neighbour data
+//
+// The sweeps read each neighbour through two packed records, written once
+// per step: vp = (u, p) of fluid particles and (u~_w, p_w) of wall and rigid
+// particles; rm = (rho, m, info bits, T).
 // ---------------------------------------------------------------------------
 
-// eq. nummeth_fluid_densum (self included) and eq. nummeth_fluid_eos
-template <typename R, int DIM>
-__global__ void __launch_bounds__(256) k_density(View<R> v, Params P, KC<R> k) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long cnt = 0;
-  if (i < P.n) {
-    const uint32_t inf = v.info[i];
-    const uint32_t kind = ikind(inf);
-    const MatT<R>& M = v.mat[iphase(inf)];
-    if (kind == KF) {
-      R sum = R(0);
-      uint32_t c = 0;
-      for_neighbors<R, DIM>(v, P, k, (uint32_t)i, true, [&](uint32_t, R, R, R, R r2) {
-        sum = sum + kern_w<R>(ksqrt(r2), k);
-        ++c;
-      });
-      const R rho = v.m[i] * sum;
-      v.rho[i] = rho;
-      if constexpr (IsExact<R>::v) v.p[i] = M.p0 * (rho / M.rho0 - R(1));
-      else v.p[i] = M.p0 * kfma(rho, M.inv_rho0, R(-1));
-      cnt = c - 1;
-    } else if (kind == KR) {
-      v.rho[i] = M.rho0;
-    }
+template <typename R>
+struct Nbr {
+  uint32_t j;
+  V4<R> vp;
+  V4<R> rm;
+};
+
+__device__ __forceinline__ float info_to_r(uint32_t v, float) { return __uint_as_float(v); }
+__device__ __forceinline__ double info_to_r(uint32_t v, double) { return (double)v; }
+__device__ __forceinline__ uint32_t r_to_info(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ uint32_t r_to_info(double v) { return (uint32_t)v; }
+
+// wall / rigid extrapolation (local force balance of Adami et al. 2012):
+// p_w = [sum p_f W + sum rho_f (b_f - a_w).(x_w - x_f) W] / sum W,
+// u~_w = 2 u_w - sum u_f W / sum W; returns the number of fluid neighbours
+template <typename R, int DIM, typename It>
+__device__ __forceinline__ uint32_t extrap_one(const View<R>& v, const KC<R>& k, uint32_t i, bool act, It&& it) {
+  const uint32_t inf = v.info[i];
+  const uint32_t kind = ikind(inf);
+  R aw[3] = {R(0), R(0), R(0)};
+  if (act && kind == KR) {
+    const V4<double> a = v.s_aw[v.aux[i]];
+    aw[0] = (R)a.x; aw[1] = (R)a.y; aw[2] = (R)a.z;
+  } else if (act && imoving(inf)) {
+    const V4<double> a = v.w_aw[v.aux[i]];
+    aw[0] = (R)a.x; aw[1] = (R)a.y; aw[2] = (R)a.z;
   }
-  block_add_pairs(v.pairs, cnt, 2);
-}
-
-// ---------------------------------------------------------------------------
-// wall / rigid extrapolation (local force balance, Adami et al. 2012)
-// ---------------------------------------------------------------------------
-
-template <typename R, int DIM>
-__global__ void __launch_bounds__(256) k_extrapolate(View<R> v, Params P, KC<R> k) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long cnt_r = 0, cnt_w = 0;
-  if (i < P.n) {
-    const uint32_t inf = v.info[i];
-    const uint32_t kind = ikind(inf);
-    if (kind != KF) {
-      R aw[3] = {R(0), R(0), R(0)};
-      if (kind == KR) {
-        const V4<double> a = v.s_aw[v.aux[i]];
-        aw[0] = (R)a.x; aw[1] = (R)a.y; aw[2] = (R)a.z;
-      } else if (imoving(inf)) {
-        const V4<double> a = v.w_aw[v.aux[i]];
-        aw[0] = (R)a.x; aw[1] = (R)a.y; aw[2] = (R)a.z;
-      }
-      R sW = R(0), sp = R(0), su0 = R(0), su1 = R(0), su2 = R(0);
-      uint32_t c = 0;
-      for_neighbors<R, DIM>(v, P, k, (uint32_t)i, false, [&](uint32_t j, R d0, R d1, R d2, R r2) {
-        const uint32_t ij = v.info[j];
-        if (ikind(ij) != KF) return;
-        ++c;
-        const MatT<R>& Mj = v.mat[iphase(ij)];
-        const R W = kern_w<R>(ksqrt(r2), k);
-        R dot;
-        if constexpr (IsExact<R>::v) {
-          dot = (Mj.b[0] - aw[0]) * d0 + (Mj.b[1] - aw[1]) * d1;
-          if (DIM == 3) dot = dot + (Mj.b[2] - aw[2]) * d2;
-        } else {
-          dot = kfma(Mj.b[1] - aw[1], d1, (Mj.b[0] - aw[0]) * d0);
-          if (DIM == 3) dot = kfma(Mj.b[2] - aw[2], d2, dot);
-        }
-        const V4<R> uj = v.u[j];
-        sW = sW + W;
-        if constexpr (IsExact<R>::v) {
-          sp = sp + (v.p[j] + v.rho[j] * dot) * W;
-          su0 = su0 + uj.x * W;
-          su1 = su1 + uj.y * W;
-          if (DIM == 3) su2 = su2 + uj.z * W;
-        } else {
-          sp = kfma(kfma(v.rho[j], dot, v.p[j]), W, sp);
-          su0 = kfma(uj.x, W, su0);
-          su1 = kfma(uj.y, W, su1);
-          if (DIM == 3) su2 = kfma(uj.z, W, su2);
-        }
-      });
-      const V4<R> ui = v.u[i];
-      V4<R> o;
-      o.w = R(0);
-      R pw;
-      if (sW > R(0)) {
-        if constexpr (IsExact<R>::v) {
-          pw = sp / sW;
-          o.x = R(2) * ui.x - su0 / sW;
-          o.y = R(2) * ui.y - su1 / sW;
-          o.z = DIM == 3 ? R(2) * ui.z - su2 / sW : R(0);
-        } else {
-          const R inv = R(1) / sW;
-          pw = sp * inv;
-          o.x = kfma(R(2), ui.x, -su0 * inv);
-          o.y = kfma(R(2), ui.y, -su1 * inv);
-          o.z = DIM == 3 ? kfma(R(2), ui.z, -su2 * inv) : R(0);
-        }
-      } else {
-        pw = R(0);
-        o.x = ui.x; o.y = ui.y; o.z = DIM == 3 ? ui.z : R(0);
-      }
-      v.pw[i] = pw;
-      v.uw[i] = o;
-      if (kind == KR) v.p[i] = pw;
-      if (kind == KR) cnt_r = c;
-      else cnt_w = c;
+  R sW = R(0), sp = R(0), su0 = R(0), su1 = R(0), su2 = R(0);
+  uint32_t c = 0;
+  it(false, [&](const Nbr<R>& nb, R d0, R d1, R d2, R r2) {
+    const uint32_t ij = r_to_info(nb.rm.z);
+    if (ikind(ij) != KF) return;
+    ++c;
+    const MatT<R>& Mj = v.mat[iphase(ij)];
+    const R W = kern_w<R>(ksqrt(r2), k);
+    R dot;
+    if constexpr (IsExact<R>::v) {
+      dot = (Mj.b[0] - aw[0]) * d0 + (Mj.b[1] - aw[1]) * d1;
+      if (DIM == 3) dot = dot + (Mj.b[2] - aw[2]) * d2;
+    } else {
+      dot = kfma(Mj.b[1] - aw[1], d1, (Mj.b[0] - aw[0]) * d0);
+      if (DIM == 3) dot = kfma(Mj.b[2] - aw[2], d2, dot);
     }
+    sW = sW + W;
+    if constexpr (IsExact<R>::v) {
+      sp = sp + (nb.vp.w + nb.rm.x * dot) * W;
+      su0 = su0 + nb.vp.x * W;
+      su1 = su1 + nb.vp.y * W;
+      if (DIM == 3) su2 = su2 + nb.vp.z * W;
+    } else {
+      sp = kfma(kfma(nb.rm.x, dot, nb.vp.w), W, sp);
+      su0 = kfma(nb.vp.x, W, su0);
+      su1 = kfma(nb.vp.y, W, su1);
+      if (DIM == 3) su2 = kfma(nb.vp.z, W, su2);
+    }
+  });
+  if (!act) return 0;
+  const V4<R> ui = v.u[i];
+  V4<R> o;
+  R pw;
+  if (sW > R(0)) {
+    if constexpr (IsExact<R>::v) {
+      pw = sp / sW;
+      o.x = R(2) * ui.x - su0 / sW;
+      o.y = R(2) * ui.y - su1 / sW;
+      o.z = DIM == 3 ? R(2) * ui.z - su2 / sW : R(0);
+    } else {
+      const R inv = R(1) / sW;
+      pw = sp * inv;
+      o.x = kfma(R(2), ui.x, -su0 * inv);
+      o.y = kfma(R(2), ui.y, -su1 * inv);
+      o.z = DIM == 3 ? kfma(R(2), ui.z, -su2 * inv) : R(0);
+    }
+  } else {
+    pw = R(0);
+    o.x = ui.x; o.y = ui.y; o.z = DIM == 3 ? ui.z : R(0);
   }
-  block_add_pairs(v.pairs, cnt_r, 3);
-  block_add_pairs(v.pairs, cnt_w, 4);
+  o.w = pw;
+  v.pw[i] = pw;
+  v.uw[i] = o;
+  v.vp[i] = o;
+  if (kind == KR) v.p[i] = pw;
+  return c;
 }
-
-// ---------------------------------------------------------------------------
-// momentum, coupling, contact and heat conduction in one gather
-// ---------------------------------------------------------------------------
 
 template <typename R>
 __device__ __forceinline__ R heat_source(const Params& P, double t, const double* x) {
@@ -394,10 +317,10 @@ __device__ __forceinline__ R heat_source(const Params& P, double t, const double
 }
 
 // Pair force F_ij = m_i a_ij of eq. nummeth_fluid_momentum for fluid "a"
-// against neighbour "b" (d = x_a - x_b); returns the three components.
+// against neighbour "b" (d = x_a - x_b)
 template <typename R, int DIM>
-__device__ __forceinline__ void pair_force(R rho_a, R p_a, R m_a, R eta_a, const V4<R>& ua, R rho_b, R p_b,
-                                           R m_b, R eta_b, const V4<R>& ub, R d0, R d1, R d2, R r, R dW,
+__device__ __forceinline__ void pair_force(R rho_a, R p_a, R m_a, R eta_a, R uax, R uay, R uaz, R rho_b, R p_b,
+                                           R m_b, R eta_b, R ubx, R uby, R ubz, R d0, R d1, R d2, R r, R dW,
                                            R* F) {
   if constexpr (IsExact<R>::v) {
     const R Va = m_a / rho_a, Vb = m_b / rho_b;
@@ -405,9 +328,9 @@ __device__ __forceinline__ void pair_force(R rho_a, R p_a, R m_a, R eta_a, const
     const R pt = (rho_b * p_a + rho_a * p_b) / (rho_a + rho_b);
     const R et = (eta_a + eta_b > R(0)) ? (R(2) * eta_a * eta_b) / (eta_a + eta_b) : R(0);
     const R c = vv * dW / r;
-    F[0] = c * (et * (ua.x - ub.x) - pt * d0);
-    F[1] = c * (et * (ua.y - ub.y) - pt * d1);
-    F[2] = DIM == 3 ? c * (et * (ua.z - ub.z) - pt * d2) : R(0);
+    F[0] = c * (et * (uax - ubx) - pt * d0);
+    F[1] = c * (et * (uay - uby) - pt * d1);
+    F[2] = DIM == 3 ? c * (et * (uaz - ubz) - pt * d2) : R(0);
   } else {
     const R Va = m_a * __builtin_amdgcn_rcpf(rho_a), Vb = m_b * __builtin_amdgcn_rcpf(rho_b);
     const R vv = kfma(Va, Va, Vb * Vb);
@@ -415,73 +338,118 @@ __device__ __forceinline__ void pair_force(R rho_a, R p_a, R m_a, R eta_a, const
     const R es = eta_a + eta_b;
     const R et = es > R(0) ? (R(2) * eta_a * eta_b) * __builtin_amdgcn_rcpf(es) : R(0);
     const R c = vv * dW * __builtin_amdgcn_rcpf(r);
-    F[0] = c * kfma(et, ua.x - ub.x, -pt * d0);
-    F[1] = c * kfma(et, ua.y - ub.y, -pt * d1);
-    F[2] = DIM == 3 ? c * kfma(et, ua.z - ub.z, -pt * d2) : R(0);
+    F[0] = c * kfma(et, uax - ubx, -pt * d0);
+    F[1] = c * kfma(et, uay - uby, -pt * d1);
+    F[2] = DIM == 3 ? c * kfma(et, uaz - ubz, -pt * d2) : R(0);
   }
 }
 
-template <typename R, int DIM, int THERMAL>
-__global__ void __launch_bounds__(256) k_forces(View<R> v, Params P, KC<R> k, int kick, int heat, double t) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P.n) return;
+// conduction term of eq. nummeth_thermo_heat_equation for one neighbour
+template <typename R>
+__device__ __forceinline__ void heat_pair(const KC<R>& k, uint32_t kj, const MatT<R>& Mj, const Nbr<R>& nb, R ka,
+                                          R Ti, R r, R dW, R& hs) {
+  R Vb;
+  if (kj == KF) Vb = kdiv(nb.rm.y, nb.rm.x);
+  else if (kj == KR) Vb = kdiv(nb.rm.y, Mj.rho0);
+  else if (Mj.dirichlet) Vb = k.vol0;
+  else return;
+  const R kb = Mj.kappa;
+  if (!(ka + kb > R(0))) return;
+  if constexpr (IsExact<R>::v) {
+    const R kk = (R(4) * ka * kb) / (ka + kb);
+    hs = hs + (Vb * kk) * ((Ti - nb.rm.w) / r) * dW;
+  } else {
+    const R kk = (R(4) * ka * kb) * __builtin_amdgcn_rcpf(ka + kb);
+    hs = kfma((Vb * kk) * ((Ti - nb.rm.w) * __builtin_amdgcn_rcpf(r)), dW, hs);
+  }
+}
+
+// Momentum (eq. nummeth_fluid_momentum) of fluid particles with the second
+// kick, coupling force f_ri = -m_i a_ir (eq. nummeth_fluid_couplingforce)
+// and spring-dashpot contact (eq. nummeth_rigid_contactforce) of rigid
+// particles, and conduction (eq. nummeth_thermo_heat_equation), in one pass
+// over the target's neighbours.  Every lane of the wave calls it (the
+// iterator synchronises); only lanes with act set have a target.
+template <typename R, int DIM, int THERMAL, typename It>
+__device__ __forceinline__ void forces_one(const View<R>& v, const Params& P, const KC<R>& k, uint32_t i, bool act,
+                                           int kick, int heat, double t, It&& it) {
   const uint32_t inf = v.info[i];
   const uint32_t kind = ikind(inf);
+  const bool fluid = kind == KF;
   const V4<R> ui = v.u[i];
-  const R Ti = v.T[i];
-  if (kind == KW) {
-    v.u_out[i] = ui;
-    if (THERMAL) v.T_out[i] = Ti;
-    return;
-  }
+  const R Ti = THERMAL ? v.T[i] : R(0);
   const MatT<R>& Mi = v.mat[iphase(inf)];
   const R m_i = v.m[i];
   const R rho_i = v.rho[i];
+  const R p_i = v.p[i];
+  const R eta_i = Mi.eta;
   const R ka = Mi.kappa;
+  const V4<R> vpr = v.vp[i];
+  const R pw_r = vpr.w;
+  const int body_i = ibody(inf);
   R acc0 = R(0), acc1 = R(0), acc2 = R(0), hs = R(0);
   bool coincident = false;
-  if (kind == KF) {
-    const R p_i = v.p[i];
-    const R eta_i = Mi.eta;
-    for_neighbors<R, DIM>(v, P, k, (uint32_t)i, false, [&](uint32_t j, R d0, R d1, R d2, R r2) {
-      if (r2 == R(0)) { coincident = true; return; }
-      const uint32_t ij = v.info[j];
-      const uint32_t kj = ikind(ij);
-      const MatT<R>& Mj = v.mat[iphase(ij)];
-      const R r = ksqrt(r2);
-      const R dW = kern_dw<R>(r, k);
+  it(false, [&](const Nbr<R>& nb, R d0, R d1, R d2, R r2) {
+    if (r2 == R(0)) { coincident = true; return; }
+    const uint32_t ij = r_to_info(nb.rm.z);
+    const uint32_t kj = ikind(ij);
+    const MatT<R>& Mj = v.mat[iphase(ij)];
+    const R r = ksqrt(r2);
+    const R dW = kern_dw<R>(r, k);
+    if (fluid) {
       R F[3];
       if (kj == KF) {
-        pair_force<R, DIM>(rho_i, p_i, m_i, eta_i, ui, v.rho[j], v.p[j], v.m[j], Mj.eta, v.u[j], d0, d1, d2, r, dW, F);
+        pair_force<R, DIM>(rho_i, p_i, m_i, eta_i, ui.x, ui.y, ui.z, nb.rm.x, nb.vp.w, nb.rm.y, Mj.eta, nb.vp.x,
+                           nb.vp.y, nb.vp.z, d0, d1, d2, r, dW, F);
       } else {
-        const R p_j = v.pw[j];
+        const R p_j = nb.vp.w;
         R rho_j;
         if constexpr (IsExact<R>::v) rho_j = Mi.rho0 * (p_j / Mi.p0 + R(1));
         else rho_j = Mi.rho0 * kfma(p_j, Mi.inv_p0, R(1));
-        pair_force<R, DIM>(rho_i, p_i, m_i, eta_i, ui, rho_j, p_j, m_i, eta_i, v.uw[j], d0, d1, d2, r, dW, F);
+        pair_force<R, DIM>(rho_i, p_i, m_i, eta_i, ui.x, ui.y, ui.z, rho_j, p_j, m_i, eta_i, nb.vp.x, nb.vp.y,
+                           nb.vp.z, d0, d1, d2, r, dW, F);
       }
       acc0 = acc0 + F[0];
       acc1 = acc1 + F[1];
       if (DIM == 3) acc2 = acc2 + F[2];
-      if (THERMAL) {
-        R Vb;
-        bool th = true;
-        if (kj == KF) Vb = kdiv(v.m[j], v.rho[j]);
-        else if (kj == KR) Vb = kdiv(v.m[j], Mj.rho0);
-        else if (Mj.dirichlet) Vb = k.vol0;
-        else th = false;
-        const R kb = Mj.kappa;
-        if (th && ka + kb > R(0)) {
-          if constexpr (IsExact<R>::v) {
-            const R kk = (R(4) * ka * kb) / (ka + kb);
-            hs = hs + (Vb * kk) * ((Ti - v.T[j]) / r) * dW;
-          } else {
-            const R kk = (R(4) * ka * kb) * __builtin_amdgcn_rcpf(ka + kb);
-            hs = kfma((Vb * kk) * ((Ti - v.T[j]) * __builtin_amdgcn_rcpf(r)), dW, hs);
-          }
-        }
+    } else if (kj == KF) {
+      const R rho_a = nb.rm.x, p_a = nb.vp.w, m_a = nb.rm.y, eta_a = Mj.eta;
+      R rho_b;
+      if constexpr (IsExact<R>::v) rho_b = Mj.rho0 * (pw_r / Mj.p0 + R(1));
+      else rho_b = Mj.rho0 * kfma(pw_r, Mj.inv_p0, R(1));
+      R F[3];
+      pair_force<R, DIM>(rho_a, p_a, m_a, eta_a, nb.vp.x, nb.vp.y, nb.vp.z, rho_b, pw_r, m_a, eta_a, vpr.x, vpr.y,
+                         vpr.z, -d0, -d1, -d2, r, dW, F);
+      acc0 = acc0 - F[0];
+      acc1 = acc1 - F[1];
+      if (DIM == 3) acc2 = acc2 - F[2];
+    } else if (P.contact && r2 < k.dx2 && (kj == KW || ibody(ij) != body_i)) {
+      const V4<R> uj = v.u[nb.j];
+      R e0, e1, e2 = R(0), en;
+      if constexpr (IsExact<R>::v) {
+        e0 = d0 / r;
+        e1 = d1 / r;
+        en = e0 * (ui.x - uj.x);
+        en = en + e1 * (ui.y - uj.y);
+        if (DIM == 3) { e2 = d2 / r; en = en + e2 * (ui.z - uj.z); }
+      } else {
+        const R ir = __builtin_amdgcn_rcpf(r);
+        e0 = d0 * ir;
+        e1 = d1 * ir;
+        en = kfma(e1, ui.y - uj.y, e0 * (ui.x - uj.x));
+        if (DIM == 3) { e2 = d2 * ir; en = kfma(e2, ui.z - uj.z, en); }
       }
-    });
+      const R fn = k.kc * (r - k.dx) + k.dc * en;
+      if (fn < R(0)) {
+        acc0 = acc0 - fn * e0;
+        acc1 = acc1 - fn * e1;
+        if (DIM == 3) acc2 = acc2 - fn * e2;
+      }
+    }
+    if (THERMAL) heat_pair<R>(k, kj, Mj, nb, ka, Ti, r, dW, hs);
+  });
+  if (!act) return;
+  if (fluid) {
     R a0, a1, a2;
     if constexpr (IsExact<R>::v) {
       a0 = acc0 / m_i + Mi.b[0];
@@ -504,69 +472,6 @@ __global__ void __launch_bounds__(256) k_forces(View<R> v, Params P, KC<R> k, in
     }
     v.u_out[i] = un;
   } else {
-    // rigid particle: coupling force f_ri = -m_i a_ir, contact
-    const R pw_r = v.pw[i];
-    const V4<R> uw_r = v.uw[i];
-    const int body_i = ibody(inf);
-    for_neighbors<R, DIM>(v, P, k, (uint32_t)i, false, [&](uint32_t j, R d0, R d1, R d2, R r2) {
-      if (r2 == R(0)) { coincident = true; return; }
-      const uint32_t ij = v.info[j];
-      const uint32_t kj = ikind(ij);
-      const MatT<R>& Mj = v.mat[iphase(ij)];
-      const R r = ksqrt(r2);
-      const R dW = kern_dw<R>(r, k);
-      if (kj == KF) {
-        const R rho_a = v.rho[j], p_a = v.p[j], m_a = v.m[j], eta_a = Mj.eta;
-        R rho_b;
-        if constexpr (IsExact<R>::v) rho_b = Mj.rho0 * (pw_r / Mj.p0 + R(1));
-        else rho_b = Mj.rho0 * kfma(pw_r, Mj.inv_p0, R(1));
-        R F[3];
-        pair_force<R, DIM>(rho_a, p_a, m_a, eta_a, v.u[j], rho_b, pw_r, m_a, eta_a, uw_r, -d0, -d1, -d2, r, dW, F);
-        acc0 = acc0 - F[0];
-        acc1 = acc1 - F[1];
-        if (DIM == 3) acc2 = acc2 - F[2];
-      } else if (P.contact && r2 < k.dx2 && (kj == KW || ibody(ij) != body_i)) {
-        const V4<R> uj = v.u[j];
-        R e0, e1, e2 = R(0), en;
-        if constexpr (IsExact<R>::v) {
-          e0 = d0 / r;
-          e1 = d1 / r;
-          en = e0 * (ui.x - uj.x);
-          en = en + e1 * (ui.y - uj.y);
-          if (DIM == 3) { e2 = d2 / r; en = en + e2 * (ui.z - uj.z); }
-        } else {
-          const R ir = __builtin_amdgcn_rcpf(r);
-          e0 = d0 * ir;
-          e1 = d1 * ir;
-          en = kfma(e1, ui.y - uj.y, e0 * (ui.x - uj.x));
-          if (DIM == 3) { e2 = d2 * ir; en = kfma(e2, ui.z - uj.z, en); }
-        }
-        const R fn = k.kc * (r - k.dx) + k.dc * en;
-        if (fn < R(0)) {
-          acc0 = acc0 - fn * e0;
-          acc1 = acc1 - fn * e1;
-          if (DIM == 3) acc2 = acc2 - fn * e2;
-        }
-      }
-      if (THERMAL) {
-        R Vb;
-        bool th = true;
-        if (kj == KF) Vb = kdiv(v.m[j], v.rho[j]);
-        else if (kj == KR) Vb = kdiv(v.m[j], Mj.rho0);
-        else if (Mj.dirichlet) Vb = k.vol0;
-        else th = false;
-        const R kb = Mj.kappa;
-        if (th && ka + kb > R(0)) {
-          if constexpr (IsExact<R>::v) {
-            const R kk = (R(4) * ka * kb) / (ka + kb);
-            hs = hs + (Vb * kk) * ((Ti - v.T[j]) / r) * dW;
-          } else {
-            const R kk = (R(4) * ka * kb) * __builtin_amdgcn_rcpf(ka + kb);
-            hs = kfma((Vb * kk) * ((Ti - v.T[j]) * __builtin_amdgcn_rcpf(r)), dW, hs);
-          }
-        }
-      }
-    });
     V4<double> f;
     f.x = (double)acc0; f.y = (double)acc1; f.z = DIM == 3 ? (double)acc2 : 0.0; f.w = 0.0;
     v.s_f[v.aux[i]] = f;
@@ -574,7 +479,7 @@ __global__ void __launch_bounds__(256) k_forces(View<R> v, Params P, KC<R> k, in
   }
   if (coincident) set_err(v.err, ERR_COINCIDENT);
   if (THERMAL) {
-    const R rho_a = kind == KF ? rho_i : Mi.rho0;
+    const R rho_a = fluid ? rho_i : Mi.rho0;
     R rate;
     if constexpr (IsExact<R>::v) rate = hs / (rho_a * Mi.cp);
     else rate = hs * __builtin_amdgcn_rcpf(rho_a * Mi.cp);
@@ -586,6 +491,388 @@ __global__ void __launch_bounds__(256) k_forces(View<R> v, Params P, KC<R> k, in
     }
     v.dTdt[i] = rate;
     v.T_out[i] = heat ? Ti + k.dt * rate : Ti;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// compact neighbour lists
+//
+// Waves are aligned to x-rows of cells: wave w holds at most 64 consecutive
+// sorted particles of one row, so its lanes share the 3 x 3 (3D) or 3 (2D)
+// stencil rows, and in each stencil row the union of the lanes' windows is
+// one contiguous range of the sorted arrays.  Every lane keeps its
+// neighbours as 16-bit entries (row << 12 | offset from the row's first
+// candidate) in the order the candidates are visited: stencil rows dz, dy
+// (outer to inner), then memory order inside a row, i.e. cells dx = -1, 0, 1
+// and ascending id -- the canonical gather order.  Waves are dispatched so
+// that each XCD works on one contiguous share of them (a spatial slab that
+// stays in its L2).
+// ---------------------------------------------------------------------------
+
+template <int DIM> struct Nb {
+  static constexpr int cap = DIM == 3 ? 160 : 48;
+  static constexpr int rows = DIM == 3 ? 9 : 3;
+};
+template <typename R> struct Win { static constexpr int v = 256; };
+template <> struct Win<double> { static constexpr int v = 128; };
+
+// workgroup b of G -> wave index, so that XCD (b mod 8) gets a contiguous range
+__device__ __forceinline__ int xcd_wave(int b, int G) {
+  const int x = b & 7, q = G >> 3, r = G & 7;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+// geometry of one wave's stencil rows
+struct WaveGeo {
+  int cy, cz, cx_first, cx_last, clo, chi;
+};
+
+template <typename R>
+__device__ __forceinline__ WaveGeo wave_geo(const View<R>& v, const Params& P, const WaveInfo& wi) {
+  WaveGeo g;
+  const int nx = P.nc[0], ny = P.nc[1];
+  g.cy = (int)(wi.row % (uint32_t)ny);
+  g.cz = (int)(wi.row / (uint32_t)ny);
+  const uint32_t rowbase = wi.row * (uint32_t)nx;
+  g.cx_first = (int)(v.cell[wi.p0] - rowbase);
+  g.cx_last = (int)(v.cell[wi.p0 + wi.cnt - 1] - rowbase);
+  g.clo = g.cx_first - 1 < 0 ? 0 : g.cx_first - 1;
+  g.chi = g.cx_last + 1 > nx - 1 ? nx - 1 : g.cx_last + 1;
+  return g;
+}
+
+// position in the wave's frame: FP64 absolute; FP32 relative to the origin
+// of cell (cx_first, cy, cz), from the cell-relative offset
+template <typename R>
+__device__ __forceinline__ V4<R> to_frame(const V4<R>& p, const KC<R>& k, int cx_first, int dy, int dz) {
+  if constexpr (IsExact<R>::v) {
+    return p;
+  } else {
+    V4<R> s;
+    s.x = kfma(p.w - (R)cx_first, k.L, p.x);
+    s.y = kfma((R)dy, k.L, p.y);
+    s.z = kfma((R)dz, k.L, p.z);
+    s.w = R(0);
+    return s;
+  }
+}
+
+template <typename R, int DIM>
+__device__ __forceinline__ R dist2(const V4<R>& T, const V4<R>& s, R& d0, R& d1, R& d2) {
+  d0 = T.x - s.x;
+  d1 = T.y - s.y;
+  d2 = R(0);
+  R r2;
+  if constexpr (IsExact<R>::v) {
+    r2 = d0 * d0 + d1 * d1;
+    if (DIM == 3) { d2 = T.z - s.z; r2 = r2 + d2 * d2; }
+  } else {
+    r2 = kfma(d1, d1, d0 * d0);
+    if (DIM == 3) { d2 = T.z - s.z; r2 = kfma(d2, d2, r2); }
+  }
+  return r2;
+}
+
+// Walk one lane's list row by row: every stencil row's window is staged in
+// LDS (positions in the wave frame and the vp / rm records), loaded with
+// coalesced reads by the whole wave; each lane then visits its entries of
+// that row from LDS.  Must be reached by all 64 lanes (it synchronises).
+template <typename R, int DIM, typename F>
+__device__ __forceinline__ void for_rows(const View<R>& v, const Params& P, const KC<R>& k, const WaveGeo& g,
+                                         V4<R>* sp, V4<R>* svp, V4<R>* srm, bool active, const uint16_t* gl,
+                                         int cnt, uint32_t i, const V4<R>& T, bool with_self, F&& visit) {
+  constexpr int NR = Nb<DIM>::rows, WIN = Win<R>::v;
+  const int lane = threadIdx.x;
+  const int nx = P.nc[0], ny = P.nc[1], nz = P.nc[2];
+  int t = 0;
+  uint32_t e = (active && cnt > 0) ? gl[0] : 0xffffu;
+  for (int rr = 0; rr < NR; ++rr) {
+    const int dz = DIM == 3 ? rr / 3 - 1 : 0, dy = rr % 3 - 1;
+    const int yy = g.cy + dy, zz = g.cz + dz;
+    if (yy < 0 || yy >= ny || zz < 0 || zz >= nz) continue;
+    const uint32_t rb2 = (uint32_t)((zz * ny + yy) * nx);
+    const uint32_t jlo = v.cstart[rb2 + g.clo], jhi = v.cstart[rb2 + g.chi + 1];
+    for (uint32_t seg = jlo; seg < jhi; seg += (uint32_t)WIN) {
+      const int ns = (int)(jhi - seg < (uint32_t)WIN ? jhi - seg : (uint32_t)WIN);
+      for (int q = lane; q < ns; q += 64) {
+        const uint32_t j = seg + (uint32_t)q;
+        sp[q] = to_frame<R>(v.pos[j], k, g.cx_first, dy, dz);
+        svp[q] = v.vp[j];
+        srm[q] = v.rm[j];
+      }
+      __syncthreads();
+      if (active) {
+        const uint32_t lo = seg - jlo, hi = lo + (uint32_t)ns;
+        while (t < cnt) {
+          if ((int)(e >> 12) != rr || (e & 0xfffu) >= hi) break;
+          const int q = (int)((e & 0xfffu) - lo);
+          const uint32_t en = (t + 1 < cnt) ? gl[(size_t)(t + 1) * 64] : 0xffffu;
+          const uint32_t j = seg + (uint32_t)q;
+          if (j != i || with_self) {
+            R d0, d1, d2;
+            const R r2 = dist2<R, DIM>(T, sp[q], d0, d1, d2);
+            Nbr<R> nb;
+            nb.j = j;
+            nb.vp = svp[q];
+            nb.rm = srm[q];
+            visit(nb, d0, d1, d2, r2);
+          }
+          e = en;
+          ++t;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_row_waves(const uint32_t* cstart, int nx, int64_t nrows, uint32_t* wcount) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  const uint32_t n = cstart[(r + 1) * nx] - cstart[r * nx];
+  wcount[r] = (n + 63u) >> 6;
+}
+
+__global__ void __launch_bounds__(256) k_row_waves_fill(const uint32_t* cstart, int nx, int64_t nrows,
+                                                        const uint32_t* woff, WaveInfo* table) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  const uint32_t s = cstart[r * nx];
+  const uint32_t n = cstart[(r + 1) * nx] - s;
+  const uint32_t w0 = woff[r];
+  for (uint32_t q = 0; q * 64u < n; ++q) {
+    WaveInfo wi;
+    wi.p0 = s + 64u * q;
+    wi.cnt = n - 64u * q < 64u ? n - 64u * q : 64u;
+    wi.row = (uint32_t)r;
+    wi.pad = 0u;
+    table[w0 + q] = wi;
+  }
+}
+
+__device__ __forceinline__ int wave_max_i(int x) {
+  for (int off = 32; off > 0; off >>= 1) {
+    int y = __shfl_xor(x, off, 64);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+// Candidate test and density: every stencil row's window is staged in LDS
+// (positions in the wave frame); every lane tests every candidate of the row
+// and appends its hits to a row-local list in LDS (branch-free: the entry is
+// always written, the count advances on a hit), sums W over the new entries
+// (eq. nummeth_fluid_densum, the particle itself included), and the row's
+// entries are appended to the lane's list in HBM for the extrapolation and
+// force sweeps.  The equation of state (eq. nummeth_fluid_eos) closes the
+// density; the packed neighbour records rm (all particles) and vp (fluid)
+// are written here.
+template <int DIM> struct RowCap { static constexpr int v = DIM == 3 ? 64 : 32; };
+
+template <typename R, int DIM>
+__global__ void __launch_bounds__(64) k_build_density(View<R> v, Params P, KC<R> k) {
+  constexpr int CAP = Nb<DIM>::cap, NR = Nb<DIM>::rows, WIN = Win<R>::v, RC = RowCap<DIM>::v;
+  __shared__ V4<R> stg[WIN];
+  __shared__ uint16_t rl[RC * 64];
+  const int w = xcd_wave(blockIdx.x, gridDim.x);
+  if (w >= (int)*v.nb.nwaves) return;
+  const WaveInfo wi = v.nb.table[w];
+  const int lane = threadIdx.x;
+  const bool active = lane < (int)wi.cnt;
+  const uint32_t i = wi.p0 + (active ? (uint32_t)lane : 0u);
+  const WaveGeo g = wave_geo<R>(v, P, wi);
+  const int nx = P.nc[0], ny = P.nc[1], nz = P.nc[2];
+  const V4<R> T = to_frame<R>(v.pos[i], k, g.cx_first, 0, 0);
+  const uint32_t inf = v.info[i];
+  const uint32_t kind = ikind(inf);
+  const bool dens = active && kind == KF;
+  // inactive lanes test against an unreachable point and never hit
+  const R far = R(1e30);
+  const R T0 = active ? T.x : far, T1 = active ? T.y : far, T2 = active ? T.z : far;
+  uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + lane;
+  int cnt = 0;
+  bool overflow = false;
+  R sum = R(0);
+  for (int rr = 0; rr < NR; ++rr) {
+    const int dz = DIM == 3 ? rr / 3 - 1 : 0, dy = rr % 3 - 1;
+    const int yy = g.cy + dy, zz = g.cz + dz;
+    uint32_t jlo = 0u, jhi = 0u;
+    if (yy >= 0 && yy < ny && zz >= 0 && zz < nz) {
+      const uint32_t rb2 = (uint32_t)((zz * ny + yy) * nx);
+      jlo = v.cstart[rb2 + g.clo];
+      jhi = v.cstart[rb2 + g.chi + 1];
+    }
+    if (lane == rr) v.nb.jlo[(size_t)w * NR + rr] = jlo;
+    int rc = 0;
+    for (uint32_t seg = jlo; seg < jhi; seg += (uint32_t)WIN) {
+      const int ns = (int)(jhi - seg < (uint32_t)WIN ? jhi - seg : (uint32_t)WIN);
+      for (int q = lane; q < ns; q += 64) stg[q] = to_frame<R>(v.pos[seg + q], k, g.cx_first, dy, dz);
+      __syncthreads();
+      const int rc0 = rc;
+      const uint32_t tag = ((uint32_t)rr << 12) | (seg - jlo);
+      int q = 0;
+      for (; q + 4 <= ns; q += 4) {
+        const V4<R> s0 = stg[q], s1 = stg[q + 1], s2 = stg[q + 2], s3 = stg[q + 3];
+        R e0, e1, e2;
+        const R a0 = dist2<R, DIM>(V4<R>{T0, T1, T2, R(0)}, s0, e0, e1, e2);
+        const R a1 = dist2<R, DIM>(V4<R>{T0, T1, T2, R(0)}, s1, e0, e1, e2);
+        const R a2 = dist2<R, DIM>(V4<R>{T0, T1, T2, R(0)}, s2, e0, e1, e2);
+        const R a3 = dist2<R, DIM>(V4<R>{T0, T1, T2, R(0)}, s3, e0, e1, e2);
+        const int slot0 = rc < RC ? rc : RC - 1;
+        rl[slot0 * 64 + lane] = (uint16_t)(tag + (uint32_t)q);
+        rc += a0 < k.rc2 ? 1 : 0;
+        const int slot1 = rc < RC ? rc : RC - 1;
+        rl[slot1 * 64 + lane] = (uint16_t)(tag + (uint32_t)q + 1u);
+        rc += a1 < k.rc2 ? 1 : 0;
+        const int slot2 = rc < RC ? rc : RC - 1;
+        rl[slot2 * 64 + lane] = (uint16_t)(tag + (uint32_t)q + 2u);
+        rc += a2 < k.rc2 ? 1 : 0;
+        const int slot3 = rc < RC ? rc : RC - 1;
+        rl[slot3 * 64 + lane] = (uint16_t)(tag + (uint32_t)q + 3u);
+        rc += a3 < k.rc2 ? 1 : 0;
+      }
+      for (; q < ns; ++q) {
+        R e0, e1, e2;
+        const R a0 = dist2<R, DIM>(V4<R>{T0, T1, T2, R(0)}, stg[q], e0, e1, e2);
+        const int slot0 = rc < RC ? rc : RC - 1;
+        rl[slot0 * 64 + lane] = (uint16_t)(tag + (uint32_t)q);
+        rc += a0 < k.rc2 ? 1 : 0;
+      }
+      if (dens) {
+        const int t1 = rc < RC ? rc : RC;
+        for (int t = rc0; t < t1; ++t) {
+          const int qq = (int)((uint32_t)rl[t * 64 + lane] & 0xfffu) - (int)(seg - jlo);
+          R d0, d1, d2;
+          const R r2 = dist2<R, DIM>(T, stg[qq], d0, d1, d2);
+          sum = sum + kern_w<R>(ksqrt(r2), k);
+        }
+      }
+      __syncthreads();
+    }
+    // append the row's entries to the lane's list in HBM
+    if (rc > RC || (int)(jhi - jlo) > 4096) overflow = true;
+    const int rcc = rc < RC ? rc : RC;
+    const int mx = wave_max_i(rcc);
+    for (int t = 0; t < mx; ++t)
+      if (t < rcc && cnt + t < CAP) gl[(size_t)(cnt + t) * 64] = rl[t * 64 + lane];
+    if (cnt + rcc > CAP) overflow = true;
+    cnt = cnt + rcc < CAP ? cnt + rcc : CAP;
+  }
+  if (overflow && active) set_err(v.err, ERR_NBCAP);
+  if (!active) cnt = 0;
+  v.nb.cnt[(size_t)w * 64 + lane] = (uint16_t)cnt;
+  unsigned long long pairs = 0;
+  if (active) {
+    const MatT<R>& M = v.mat[iphase(inf)];
+    R rho;
+    if (kind == KF) {
+      rho = v.m[i] * sum;
+      R p;
+      if constexpr (IsExact<R>::v) p = M.p0 * (rho / M.rho0 - R(1));
+      else p = M.p0 * kfma(rho, M.inv_rho0, R(-1));
+      v.p[i] = p;
+      V4<R> vp = v.u[i];
+      vp.w = p;
+      v.vp[i] = vp;
+      pairs = (unsigned long long)(cnt - 1);
+    } else {
+      rho = kind == KR ? M.rho0 : R(0);
+      if (kind == KW) v.p[i] = R(0);
+    }
+    v.rho[i] = rho;
+    V4<R> rm;
+    rm.x = rho;
+    rm.y = v.m[i];
+    rm.z = info_to_r(inf, R(0));
+    rm.w = P.thermal ? v.T[i] : R(0);
+    v.rm[i] = rm;
+  }
+  block_add_pairs(v.pairs, pairs, 2);
+}
+
+template <typename R, int DIM>
+__global__ void __launch_bounds__(64) k_extrapolate_list(View<R> v, Params P, KC<R> k) {
+  constexpr int CAP = Nb<DIM>::cap, WIN = Win<R>::v;
+  __shared__ V4<R> sp[WIN], svp[WIN], srm[WIN];
+  const int w = xcd_wave(blockIdx.x, gridDim.x);
+  if (w >= (int)*v.nb.nwaves) return;
+  const WaveInfo wi = v.nb.table[w];
+  const int lane = threadIdx.x;
+  const bool active = lane < (int)wi.cnt;
+  const uint32_t i = wi.p0 + (active ? (uint32_t)lane : 0u);
+  const uint32_t kind = ikind(v.info[i]);
+  const bool need = active && kind != KF;
+  if (!__any(need)) return;
+  const WaveGeo g = wave_geo<R>(v, P, wi);
+  const V4<R> T = to_frame<R>(v.pos[i], k, g.cx_first, 0, 0);
+  const int cnt = need ? (int)v.nb.cnt[(size_t)w * 64 + lane] : 0;
+  const uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + lane;
+  unsigned long long cr = 0, cw = 0;
+  const uint32_t c = extrap_one<R, DIM>(v, k, i, need, [&](bool ws, auto&& f) {
+    for_rows<R, DIM>(v, P, k, g, sp, svp, srm, need, gl, cnt, i, T, ws, f);
+  });
+  if (need && kind == KR) cr = c;
+  else if (need) cw = c;
+  block_add_pairs(v.pairs, cr, 3);
+  block_add_pairs(v.pairs, cw, 4);
+}
+
+template <typename R, int DIM, int THERMAL>
+__global__ void __launch_bounds__(64) k_forces_list(View<R> v, Params P, KC<R> k, int kick, int heat, double t) {
+  constexpr int CAP = Nb<DIM>::cap, WIN = Win<R>::v;
+  __shared__ V4<R> sp[WIN], svp[WIN], srm[WIN];
+  const int w = xcd_wave(blockIdx.x, gridDim.x);
+  if (w >= (int)*v.nb.nwaves) return;
+  const WaveInfo wi = v.nb.table[w];
+  const int lane = threadIdx.x;
+  const bool active = lane < (int)wi.cnt;
+  const uint32_t i = wi.p0 + (active ? (uint32_t)lane : 0u);
+  const uint32_t kind = ikind(v.info[i]);
+  const WaveGeo g = wave_geo<R>(v, P, wi);
+  if (active && kind == KW) {
+    v.u_out[i] = v.u[i];
+    if (THERMAL) v.T_out[i] = v.T[i];
+  }
+  const bool need = active && kind != KW;
+  if (!__any(need)) return;
+  const V4<R> T = to_frame<R>(v.pos[i], k, g.cx_first, 0, 0);
+  const int cnt = need ? (int)v.nb.cnt[(size_t)w * 64 + lane] : 0;
+  const uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + lane;
+  forces_one<R, DIM, THERMAL>(v, P, k, i, need, kick, heat, t, [&](bool ws, auto&& f) {
+    for_rows<R, DIM>(v, P, k, g, sp, svp, srm, need, gl, cnt, i, T, ws, f);
+  });
+}
+
+// neighbour export from the lists (diagnostic): counts, then ids
+template <typename R, int DIM>
+__global__ void __launch_bounds__(64) k_list_count(View<R> v, Params P, uint32_t* out) {
+  const int w = blockIdx.x;
+  if (w >= (int)*v.nb.nwaves) return;
+  const WaveInfo wi = v.nb.table[w];
+  const int lane = threadIdx.x;
+  if (lane >= (int)wi.cnt) return;
+  const uint32_t i = wi.p0 + (uint32_t)lane;
+  const int cnt = v.nb.cnt[(size_t)w * 64 + lane];
+  out[v.id[i]] = cnt > 0 ? (uint32_t)(cnt - 1) : 0u;
+}
+
+template <typename R, int DIM>
+__global__ void __launch_bounds__(64) k_list_fill(View<R> v, Params P, const uint64_t* off, uint32_t* ids) {
+  constexpr int CAP = Nb<DIM>::cap, NR = Nb<DIM>::rows;
+  const int w = blockIdx.x;
+  if (w >= (int)*v.nb.nwaves) return;
+  const WaveInfo wi = v.nb.table[w];
+  const int lane = threadIdx.x;
+  if (lane >= (int)wi.cnt) return;
+  const uint32_t i = wi.p0 + (uint32_t)lane;
+  const int cnt = v.nb.cnt[(size_t)w * 64 + lane];
+  const uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + lane;
+  const uint32_t* jlo = v.nb.jlo + (size_t)w * NR;
+  uint64_t o = off[v.id[i]];
+  for (int q = 0; q < cnt; ++q) {
+    const uint32_t e = gl[(size_t)q * 64];
+    const uint32_t j = jlo[e >> 12] + (e & 0xfffu);
+    if (j != i) ids[o++] = v.id[j];
   }
 }
 
@@ -636,7 +923,7 @@ __global__ void __launch_bounds__(256) k_kick_drift(View<R> v, Params P, KC<R> k
         if (c3[a] >= P.nc[a]) { c3[a] = P.nc[a] - 1; esc = true; }
       }
       if (esc || !isfinite(o[0]) || !isfinite(o[1]) || !isfinite(o[2])) set_err(v.err, esc ? ERR_ESCAPE : ERR_NONFINITE);
-      x.x = o[0]; x.y = o[1]; x.z = o[2];
+      x.x = o[0]; x.y = o[1]; x.z = o[2]; x.w = (R)c3[0];
       c = (uint32_t)((long long)c3[0] + (long long)P.nc[0] * ((long long)c3[1] + (long long)P.nc[1] * c3[2]));
       v.cell[i] = c;
     }
@@ -1192,27 +1479,6 @@ __global__ void __launch_bounds__(256) k_global_final(const double* part, int nb
 }
 
 // ---------------------------------------------------------------------------
-// neighbour export (diagnostic)
-// ---------------------------------------------------------------------------
-
-template <typename R, int DIM>
-__global__ void __launch_bounds__(256) k_nb_count(View<R> v, Params P, KC<R> k, uint32_t* cnt) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P.n) return;
-  uint32_t c = 0;
-  for_neighbors<R, DIM>(v, P, k, (uint32_t)i, false, [&](uint32_t, R, R, R, R) { ++c; });
-  cnt[v.id[i]] = c;
-}
-
-template <typename R, int DIM>
-__global__ void __launch_bounds__(256) k_nb_fill(View<R> v, Params P, KC<R> k, const uint64_t* off, uint32_t* ids) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P.n) return;
-  uint64_t o = off[v.id[i]];
-  for_neighbors<R, DIM>(v, P, k, (uint32_t)i, false, [&](uint32_t j, R, R, R, R) { ids[o++] = v.id[j]; });
-}
-
-// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 
@@ -1222,14 +1488,25 @@ void launch_fill_u32(uint32_t* p, uint32_t val, int64_t n, hipStream_t st) {
   if (n > 0) k_fill_u32<<<nblk(n), 256, 0, st>>>(p, val, n);
 }
 
+void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum, hipStream_t st) {
+  const int64_t nb = (n + 1023) / 1024;
+  if (nb > 0) k_scan_blocks<<<(unsigned)nb, 256, 0, st>>>(in, out, bsum, n);
+  k_scan_bsum<<<1, 256, 0, st>>>(bsum, nb, out + n);
+  if (nb > 0) k_scan_add<<<(unsigned)nb, 256, 0, st>>>(out, bsum, n);
+}
+
+void launch_wave_table(const Params& P, const uint32_t* cstart, uint32_t* wcount, uint32_t* woff, uint32_t* bsum,
+                       WaveInfo* table, hipStream_t st) {
+  k_row_waves<<<nblk(P.nrows), 256, 0, st>>>(cstart, P.nc[0], P.nrows, wcount);
+  launch_scan_u32(wcount, woff, P.nrows, bsum, st);
+  k_row_waves_fill<<<nblk(P.nrows), 256, 0, st>>>(cstart, P.nc[0], P.nrows, woff, table);
+}
+
 void launch_sort_keys(const Params& P, SortBufs sb, uint32_t* cstart, const uint32_t* id, hipStream_t st) {
   const int64_t C = P.ncells, n = P.n;
   launch_fill_u32(sb.ccount, 0u, C, st);
   if (n > 0) k_count<<<nblk(n), 256, 0, st>>>(sb.key, sb.ccount, sb.rank, n);
-  const int64_t nb = (C + 1023) / 1024;
-  k_scan_blocks<<<(unsigned)nb, 256, 0, st>>>(sb.ccount, cstart, sb.bsum, C);
-  k_scan_bsum<<<1, 256, 0, st>>>(sb.bsum, nb, cstart + C);
-  k_scan_add<<<(unsigned)nb, 256, 0, st>>>(cstart, sb.bsum, C);
+  launch_scan_u32(sb.ccount, cstart, C, sb.bsum, st);
   if (n > 0) {
     k_scatter<<<nblk(n), 256, 0, st>>>(sb.key, sb.rank, cstart, id, sb.tid, sb.tsrc, n);
   }
@@ -1275,26 +1552,28 @@ void Launch<R>::gather(const View<R>& src, const View<R>& dst, const Params& P, 
 template <typename R>
 void Launch<R>::density(const View<R>& v, const Params& P, const KC<R>& k, hipStream_t st) {
   if (P.n <= 0) return;
-  if (P.dim == 2) k_density<R, 2><<<nblk(P.n), 256, 0, st>>>(v, P, k);
-  else k_density<R, 3><<<nblk(P.n), 256, 0, st>>>(v, P, k);
+  const unsigned g = (unsigned)P.max_waves;
+  if (P.dim == 2) k_build_density<R, 2><<<g, 64, 0, st>>>(v, P, k);
+  else k_build_density<R, 3><<<g, 64, 0, st>>>(v, P, k);
 }
 template <typename R>
 void Launch<R>::extrapolate(const View<R>& v, const Params& P, const KC<R>& k, hipStream_t st) {
   if (P.n <= 0) return;
-  if (P.dim == 2) k_extrapolate<R, 2><<<nblk(P.n), 256, 0, st>>>(v, P, k);
-  else k_extrapolate<R, 3><<<nblk(P.n), 256, 0, st>>>(v, P, k);
+  const unsigned g = (unsigned)P.max_waves;
+  if (P.dim == 2) k_extrapolate_list<R, 2><<<g, 64, 0, st>>>(v, P, k);
+  else k_extrapolate_list<R, 3><<<g, 64, 0, st>>>(v, P, k);
 }
 template <typename R>
 void Launch<R>::forces(const View<R>& v, const Params& P, const KC<R>& k, int kick, int heat, double t,
                        hipStream_t st) {
   if (P.n <= 0) return;
-  const unsigned g = nblk(P.n);
+  const unsigned g = (unsigned)P.max_waves;
   if (P.thermal) {
-    if (P.dim == 2) k_forces<R, 2, 1><<<g, 256, 0, st>>>(v, P, k, kick, heat, t);
-    else k_forces<R, 3, 1><<<g, 256, 0, st>>>(v, P, k, kick, heat, t);
+    if (P.dim == 2) k_forces_list<R, 2, 1><<<g, 64, 0, st>>>(v, P, k, kick, heat, t);
+    else k_forces_list<R, 3, 1><<<g, 64, 0, st>>>(v, P, k, kick, heat, t);
   } else {
-    if (P.dim == 2) k_forces<R, 2, 0><<<g, 256, 0, st>>>(v, P, k, kick, heat, t);
-    else k_forces<R, 3, 0><<<g, 256, 0, st>>>(v, P, k, kick, heat, t);
+    if (P.dim == 2) k_forces_list<R, 2, 0><<<g, 64, 0, st>>>(v, P, k, kick, heat, t);
+    else k_forces_list<R, 3, 0><<<g, 64, 0, st>>>(v, P, k, kick, heat, t);
   }
 }
 template <typename R>
@@ -1308,17 +1587,17 @@ void Launch<R>::global_sums(const View<R>& v, const Params& P, double* partials,
   k_global_final<<<1, 256, 0, st>>>(partials, nblocks, out);
 }
 template <typename R>
-void Launch<R>::nb_count(const View<R>& v, const Params& P, const KC<R>& k, uint32_t* cnt, hipStream_t st) {
+void Launch<R>::nb_count(const View<R>& v, const Params& P, const KC<R>&, uint32_t* cnt, hipStream_t st) {
   if (P.n <= 0) return;
-  if (P.dim == 2) k_nb_count<R, 2><<<nblk(P.n), 256, 0, st>>>(v, P, k, cnt);
-  else k_nb_count<R, 3><<<nblk(P.n), 256, 0, st>>>(v, P, k, cnt);
+  if (P.dim == 2) k_list_count<R, 2><<<(unsigned)P.max_waves, 64, 0, st>>>(v, P, cnt);
+  else k_list_count<R, 3><<<(unsigned)P.max_waves, 64, 0, st>>>(v, P, cnt);
 }
 template <typename R>
-void Launch<R>::nb_fill(const View<R>& v, const Params& P, const KC<R>& k, const uint64_t* off, uint32_t* ids,
+void Launch<R>::nb_fill(const View<R>& v, const Params& P, const KC<R>&, const uint64_t* off, uint32_t* ids,
                         hipStream_t st) {
   if (P.n <= 0) return;
-  if (P.dim == 2) k_nb_fill<R, 2><<<nblk(P.n), 256, 0, st>>>(v, P, k, off, ids);
-  else k_nb_fill<R, 3><<<nblk(P.n), 256, 0, st>>>(v, P, k, off, ids);
+  if (P.dim == 2) k_list_fill<R, 2><<<(unsigned)P.max_waves, 64, 0, st>>>(v, P, off, ids);
+  else k_list_fill<R, 3><<<(unsigned)P.max_waves, 64, 0, st>>>(v, P, off, ids);
 }
 template <typename R>
 void Launch<R>::slot_positions(const View<R>& v, const Params& P, hipStream_t st) {
