@@ -73,13 +73,16 @@ struct WaveInfo {
   uint32_t p0, cnt, row, pad;
 };
 
-// compact neighbour lists, [wave][entry][lane] (16-bit entries), per-lane
-// counts and per-wave first candidate index of every stencil row
+// compact neighbour lists, [wave][entry][lane] (16-bit entries); the
+// entries of stencil row rr start at entry rbase[wave][rr] for every lane,
+// rcnt[wave][rr][lane] of them belong to the lane; jlo is the first
+// candidate index of every stencil row
 struct Lists {
   WaveInfo* table;
   uint32_t* nwaves;
   uint16_t* ent;
-  uint16_t* cnt;
+  uint8_t* rcnt;
+  uint16_t* rbase;
   uint32_t* jlo;
 };
 

@@ -510,7 +510,7 @@ __device__ __forceinline__ void forces_one(const View<R>& v, const Params& P, co
 // ---------------------------------------------------------------------------
 
 template <int DIM> struct Nb {
-  static constexpr int cap = DIM == 3 ? 160 : 48;
+  static constexpr int cap = DIM == 3 ? 320 : 64;
   static constexpr int rows = DIM == 3 ? 9 : 3;
 };
 template <typename R> struct Win { static constexpr int v = 256; };
@@ -579,19 +579,22 @@ __device__ __forceinline__ R dist2(const V4<R>& T, const V4<R>& s, R& d0, R& d1,
 // that row from LDS.  Must be reached by all 64 lanes (it synchronises).
 template <typename R, int DIM, typename F>
 __device__ __forceinline__ void for_rows(const View<R>& v, const Params& P, const KC<R>& k, const WaveGeo& g,
-                                         V4<R>* sp, V4<R>* svp, V4<R>* srm, bool active, const uint16_t* gl,
-                                         int cnt, uint32_t i, const V4<R>& T, bool with_self, F&& visit) {
-  constexpr int NR = Nb<DIM>::rows, WIN = Win<R>::v;
+                                         V4<R>* sp, V4<R>* svp, V4<R>* srm, bool active, int w, uint32_t i,
+                                         const V4<R>& T, bool with_self, F&& visit) {
+  constexpr int NR = Nb<DIM>::rows, WIN = Win<R>::v, CAP = Nb<DIM>::cap;
   const int lane = threadIdx.x;
   const int nx = P.nc[0], ny = P.nc[1], nz = P.nc[2];
-  int t = 0;
-  uint32_t e = (active && cnt > 0) ? gl[0] : 0xffffu;
+  const uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + lane;
   for (int rr = 0; rr < NR; ++rr) {
     const int dz = DIM == 3 ? rr / 3 - 1 : 0, dy = rr % 3 - 1;
     const int yy = g.cy + dy, zz = g.cz + dz;
     if (yy < 0 || yy >= ny || zz < 0 || zz >= nz) continue;
     const uint32_t rb2 = (uint32_t)((zz * ny + yy) * nx);
     const uint32_t jlo = v.cstart[rb2 + g.clo], jhi = v.cstart[rb2 + g.chi + 1];
+    const int tb = v.nb.rbase[(size_t)w * NR + rr];
+    const int c = active ? (int)v.nb.rcnt[((size_t)w * NR + rr) * 64 + lane] : 0;
+    int t = 0;
+    uint32_t e = c > 0 ? gl[(size_t)tb * 64] : 0xffffu;
     for (uint32_t seg = jlo; seg < jhi; seg += (uint32_t)WIN) {
       const int ns = (int)(jhi - seg < (uint32_t)WIN ? jhi - seg : (uint32_t)WIN);
       for (int q = lane; q < ns; q += 64) {
@@ -601,25 +604,23 @@ __device__ __forceinline__ void for_rows(const View<R>& v, const Params& P, cons
         srm[q] = v.rm[j];
       }
       __syncthreads();
-      if (active) {
-        const uint32_t lo = seg - jlo, hi = lo + (uint32_t)ns;
-        while (t < cnt) {
-          if ((int)(e >> 12) != rr || (e & 0xfffu) >= hi) break;
-          const int q = (int)((e & 0xfffu) - lo);
-          const uint32_t en = (t + 1 < cnt) ? gl[(size_t)(t + 1) * 64] : 0xffffu;
-          const uint32_t j = seg + (uint32_t)q;
-          if (j != i || with_self) {
-            R d0, d1, d2;
-            const R r2 = dist2<R, DIM>(T, sp[q], d0, d1, d2);
-            Nbr<R> nb;
-            nb.j = j;
-            nb.vp = svp[q];
-            nb.rm = srm[q];
-            visit(nb, d0, d1, d2, r2);
-          }
-          e = en;
-          ++t;
+      const uint32_t lo = seg - jlo, hi = lo + (uint32_t)ns;
+      while (t < c) {
+        if ((e & 0xfffu) >= hi) break;
+        const int q = (int)((e & 0xfffu) - lo);
+        const uint32_t en = (t + 1 < c) ? gl[(size_t)(tb + t + 1) * 64] : 0xffffu;
+        const uint32_t j = seg + (uint32_t)q;
+        if (j != i || with_self) {
+          R d0, d1, d2;
+          const R r2 = dist2<R, DIM>(T, sp[q], d0, d1, d2);
+          Nbr<R> nb;
+          nb.j = j;
+          nb.vp = svp[q];
+          nb.rm = srm[q];
+          visit(nb, d0, d1, d2, r2);
         }
+        e = en;
+        ++t;
       }
       __syncthreads();
     }
@@ -690,7 +691,7 @@ __global__ void __launch_bounds__(64) k_build_density(View<R> v, Params P, KC<R>
   const R far = R(1e30);
   const R T0 = active ? T.x : far, T1 = active ? T.y : far, T2 = active ? T.z : far;
   uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + lane;
-  int cnt = 0;
+  int cnt = 0, tb = 0;
   bool overflow = false;
   R sum = R(0);
   for (int rr = 0; rr < NR; ++rr) {
@@ -703,7 +704,7 @@ __global__ void __launch_bounds__(64) k_build_density(View<R> v, Params P, KC<R>
       jhi = v.cstart[rb2 + g.chi + 1];
     }
     if (lane == rr) v.nb.jlo[(size_t)w * NR + rr] = jlo;
-    int rc = 0;
+  int rc = 0;
     for (uint32_t seg = jlo; seg < jhi; seg += (uint32_t)WIN) {
       const int ns = (int)(jhi - seg < (uint32_t)WIN ? jhi - seg : (uint32_t)WIN);
       for (int q = lane; q < ns; q += 64) stg[q] = to_frame<R>(v.pos[seg + q], k, g.cx_first, dy, dz);
@@ -749,18 +750,20 @@ __global__ void __launch_bounds__(64) k_build_density(View<R> v, Params P, KC<R>
       }
       __syncthreads();
     }
-    // append the row's entries to the lane's list in HBM
+    // the row's entries go to HBM as one block shared by all lanes
     if (rc > RC || (int)(jhi - jlo) > 4096) overflow = true;
     const int rcc = rc < RC ? rc : RC;
     const int mx = wave_max_i(rcc);
-    for (int t = 0; t < mx; ++t)
-      if (t < rcc && cnt + t < CAP) gl[(size_t)(cnt + t) * 64] = rl[t * 64 + lane];
-    if (cnt + rcc > CAP) overflow = true;
-    cnt = cnt + rcc < CAP ? cnt + rcc : CAP;
+    const int nw = tb + mx <= CAP ? mx : CAP - tb;
+    if (tb + mx > CAP) overflow = true;
+    for (int t = 0; t < nw; ++t) gl[(size_t)(tb + t) * 64] = rl[t * 64 + lane];
+    v.nb.rcnt[((size_t)w * NR + rr) * 64 + lane] = (uint8_t)(active ? (rcc < nw ? rcc : nw) : 0);
+    if (lane == 0) v.nb.rbase[(size_t)w * NR + rr] = (uint16_t)tb;
+    tb += nw;
+    cnt += active ? rcc : 0;
   }
   if (overflow && active) set_err(v.err, ERR_NBCAP);
   if (!active) cnt = 0;
-  v.nb.cnt[(size_t)w * 64 + lane] = (uint16_t)cnt;
   unsigned long long pairs = 0;
   if (active) {
     const MatT<R>& M = v.mat[iphase(inf)];
@@ -805,11 +808,9 @@ __global__ void __launch_bounds__(64) k_extrapolate_list(View<R> v, Params P, KC
   if (!__any(need)) return;
   const WaveGeo g = wave_geo<R>(v, P, wi);
   const V4<R> T = to_frame<R>(v.pos[i], k, g.cx_first, 0, 0);
-  const int cnt = need ? (int)v.nb.cnt[(size_t)w * 64 + lane] : 0;
-  const uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + lane;
   unsigned long long cr = 0, cw = 0;
   const uint32_t c = extrap_one<R, DIM>(v, k, i, need, [&](bool ws, auto&& f) {
-    for_rows<R, DIM>(v, P, k, g, sp, svp, srm, need, gl, cnt, i, T, ws, f);
+    for_rows<R, DIM>(v, P, k, g, sp, svp, srm, need, w, i, T, ws, f);
   });
   if (need && kind == KR) cr = c;
   else if (need) cw = c;
@@ -836,24 +837,24 @@ __global__ void __launch_bounds__(64) k_forces_list(View<R> v, Params P, KC<R> k
   const bool need = active && kind != KW;
   if (!__any(need)) return;
   const V4<R> T = to_frame<R>(v.pos[i], k, g.cx_first, 0, 0);
-  const int cnt = need ? (int)v.nb.cnt[(size_t)w * 64 + lane] : 0;
-  const uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + lane;
   forces_one<R, DIM, THERMAL>(v, P, k, i, need, kick, heat, t, [&](bool ws, auto&& f) {
-    for_rows<R, DIM>(v, P, k, g, sp, svp, srm, need, gl, cnt, i, T, ws, f);
+    for_rows<R, DIM>(v, P, k, g, sp, svp, srm, need, w, i, T, ws, f);
   });
 }
 
 // neighbour export from the lists (diagnostic): counts, then ids
 template <typename R, int DIM>
 __global__ void __launch_bounds__(64) k_list_count(View<R> v, Params P, uint32_t* out) {
+  constexpr int NR = Nb<DIM>::rows;
   const int w = blockIdx.x;
   if (w >= (int)*v.nb.nwaves) return;
   const WaveInfo wi = v.nb.table[w];
   const int lane = threadIdx.x;
   if (lane >= (int)wi.cnt) return;
   const uint32_t i = wi.p0 + (uint32_t)lane;
-  const int cnt = v.nb.cnt[(size_t)w * 64 + lane];
-  out[v.id[i]] = cnt > 0 ? (uint32_t)(cnt - 1) : 0u;
+  uint32_t c = 0;
+  for (int rr = 0; rr < NR; ++rr) c += v.nb.rcnt[((size_t)w * NR + rr) * 64 + lane];
+  out[v.id[i]] = c > 0 ? c - 1 : 0u;
 }
 
 template <typename R, int DIM>
@@ -865,14 +866,17 @@ __global__ void __launch_bounds__(64) k_list_fill(View<R> v, Params P, const uin
   const int lane = threadIdx.x;
   if (lane >= (int)wi.cnt) return;
   const uint32_t i = wi.p0 + (uint32_t)lane;
-  const int cnt = v.nb.cnt[(size_t)w * 64 + lane];
   const uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + lane;
   const uint32_t* jlo = v.nb.jlo + (size_t)w * NR;
   uint64_t o = off[v.id[i]];
-  for (int q = 0; q < cnt; ++q) {
-    const uint32_t e = gl[(size_t)q * 64];
-    const uint32_t j = jlo[e >> 12] + (e & 0xfffu);
-    if (j != i) ids[o++] = v.id[j];
+  for (int rr = 0; rr < NR; ++rr) {
+    const int tb = v.nb.rbase[(size_t)w * NR + rr];
+    const int c = v.nb.rcnt[((size_t)w * NR + rr) * 64 + lane];
+    for (int q = 0; q < c; ++q) {
+      const uint32_t e = gl[(size_t)(tb + q) * 64];
+      const uint32_t j = jlo[rr] + (e & 0xfffu);
+      if (j != i) ids[o++] = v.id[j];
+    }
   }
 }
 

@@ -33,9 +33,9 @@ def test_arena_bytes_scale_with_precision_and_size():
     assert 0 < b32 < b64
     big = S.fluid_box(3, 20)
     assert B.sph_scene_arena_bytes(B.Desc(big, B.SPH_FP32_SWEEP)) > b32
-    # FP32 footprint per particle (state, sort buffers and the fixed-capacity
-    # neighbour lists of 160 16-bit entries per particle in 3D)
-    assert B.sph_scene_arena_bytes(B.Desc(big, B.SPH_FP32_SWEEP)) / big.n < 800
+    # FP32 footprint per particle: state, sort buffers and the fixed-capacity
+    # neighbour lists (320 16-bit entries per particle in 3D)
+    assert B.sph_scene_arena_bytes(B.Desc(big, B.SPH_FP32_SWEEP)) / big.n < 1500
 
 
 @pytest.mark.parametrize("mutate,what", [
