@@ -99,6 +99,9 @@ struct sph_scene {
   unsigned long long* pairs;
   Lists nb;
   uint32_t *wcount, *woff, *wbsum;
+  uint32_t* dyn;     // device: [0] rigid particles, [1] bodies
+  double* matb;      // device: body force of every material (FP64)
+  PhaseBufs ps;
   double* gpart;
   double* gout;
   // timers: SPH_TIMER_STAGES + 1 events per recorded step
@@ -232,7 +235,7 @@ void carve(Carver& cv, sph_scene* s, const Params& P, int64_t nmat) {
   s->sb.nbsum = (P.ncells + 1023) / 1024;
   s->sb.bsum = cv.take<uint32_t>((size_t)s->sb.nbsum + 1);
   s->cstart = cv.take<uint32_t>((size_t)P.ncells + 1);
-  const size_t nr = (size_t)P.n_rigid, nw = (size_t)P.n_moving;
+  const size_t nr = (size_t)P.slot_cap, nw = (size_t)P.n_moving;
   s->s_rb = cv.take<V4<double>>(nr);
   s->s_rk = cv.take<V4<double>>(nr);
   s->s_f = cv.take<V4<double>>(nr);
@@ -262,6 +265,34 @@ void carve(Carver& cv, sph_scene* s, const Params& P, int64_t nmat) {
   s->nb.nwaves = s->woff + P.nrows;
   s->gpart = cv.take<double>(5 * kGlobalBlocks);
   s->gout = cv.take<double>(8);
+  s->dyn = cv.take<uint32_t>(4);
+  s->matb = cv.take<double>(3 * (size_t)nmat);
+  // phase switch work space (only with switching enabled)
+  const size_t np = P.pswitch ? n : 0, nbp = P.pswitch ? (size_t)std::max(P.maxb, 1) : 0;
+  PhaseBufs& ps = s->ps;
+  ps.flag = cv.take<uint8_t>(np);
+  ps.target = cv.take<int32_t>(np);
+  ps.label = cv.take<uint32_t>(np);
+  ps.body_of_id = cv.take<uint32_t>(np);
+  ps.list = cv.take<uint32_t>(np);
+  ps.roots = cv.take<uint32_t>(np);
+  ps.ctr = cv.take<uint32_t>(8);
+  ps.dirty = cv.take<uint32_t>(nbp);
+  ps.rold = cv.take<V4<double>>(nbp);
+  ps.alive = cv.take<uint32_t>(P.pswitch ? nr : 0);
+  ps.alive_sc = cv.take<uint32_t>(P.pswitch ? nr + 1 : 0);
+  ps.bsum = cv.take<uint32_t>(P.pswitch ? (nr + 1023) / 1024 + 1 : 0);
+  for (int b = 0; b < 2; ++b) {
+    ps.jkey[b] = cv.take<unsigned long long>(np);
+    ps.jidx[b] = cv.take<uint32_t>(np);
+  }
+  const size_t ns = P.pswitch ? nr : 0;
+  ps.snew = cv.take<uint32_t>(ns);
+  ps.sbody = cv.take<int32_t>(ns);
+  ps.sid = cv.take<uint32_t>(ns);
+  ps.srb = cv.take<V4<double>>(ns);
+  ps.srk = cv.take<V4<double>>(ns);
+  ps.srf = cv.take<V4<double>>(ns);
 }
 
 int make_params(const sph_scene_desc* d, Params& P, double* m_min) {
@@ -332,6 +363,10 @@ int make_params(const sph_scene_desc* d, Params& P, double* m_min) {
   P.n_moving = c.n_moving;
   P.nrows = (int64_t)P.nc[1] * P.nc[2];
   P.max_waves = (P.n + 63) / 64 + P.nrows + 1;
+  // with phase switching every particle may become rigid and every body
+  // slot up to max_bodies may be in use
+  P.slot_cap = P.pswitch ? P.n : P.n_rigid;
+  P.body_launch = P.pswitch ? P.maxb : P.nb;
   *m_min = mmin;
   return SPH_OK;
 }
@@ -395,6 +430,8 @@ View<R> make_view(sph_scene* s, int ip, int iu, int iT) {
   v.err = s->err;
   v.pairs = s->pairs;
   v.nb = s->nb;
+  v.dyn = s->dyn;
+  v.ps = s->ps;
   return v;
 }
 
@@ -437,7 +474,7 @@ void evaluate(sph_scene* s, int kick, int heat, double t, hipEvent_t* ev) {
   if (ev) (void)hipEventRecord(ev[5], s->stream);
   s->iu = 1 - s->iu;
   if (s->P.thermal) s->iT = 1 - s->iT;
-  launch_body_reduce(s->bodies, s->s_f, s->s_rk, s->P, kick, s->stream);
+  launch_body_reduce(s->bodies, s->s_f, s->s_rk, s->P, kick, s->P.pswitch ? s->dyn + 1 : nullptr, s->stream);
   if (ev) (void)hipEventRecord(ev[6], s->stream);
 }
 
@@ -452,7 +489,7 @@ void one_step(sph_scene* s) {
   if (ev) (void)hipEventRecord(ev[0], s->stream);
   View<R> v = cur<R>(s);
   Launch<R>::kick_drift(v, P, k, s->sb, s->stream);
-  launch_body_kick_drift(s->bodies, P, s->stream);
+  launch_body_kick_drift(s->bodies, P, P.pswitch ? s->dyn + 1 : nullptr, s->stream);
   Launch<R>::rigid_pose(v, P, k, s->sb, t_new, s->stream);
   Launch<R>::wall_motion(v, P, k, s->sb, t_new, s->stream);
   if (ev) (void)hipEventRecord(ev[1], s->stream);
@@ -461,6 +498,7 @@ void one_step(sph_scene* s) {
   evaluate<R>(s, 1, 1, t_new, ev);
   v = cur<R>(s);
   Launch<R>::rigid_velocity(v, P, s->stream);
+  if (P.pswitch) Launch<R>::phase_switch(v, P, k, s->matb, s->stream);
   if (ev) {
     (void)hipEventRecord(ev[7], s->stream);
     s->rec += 1;
@@ -602,6 +640,10 @@ int create_impl(const sph_scene_desc* d, sph_scene* s) {
     bodies[kb].q[0] = 1.0;
     bodies[kb].slot0 = (int32_t)P.n_rigid;
   }
+  std::vector<double> matb(3 * (size_t)d->n_mat);
+  for (int k = 0; k < d->n_mat; ++k)
+    for (int ax = 0; ax < 3; ++ax) matb[3 * k + ax] = ax < d->dim ? d->mat[k].b[ax] : 0.0;
+  const uint32_t dyn[4] = {(uint32_t)P.n_rigid, (uint32_t)P.nb, 0u, 0u};
   // upload into buffer set 0
   if (n > 0) {
     HIP_TRY(hipMemcpyAsync(s->pos[0], pos.data(), sizeof(V4<R>) * n, hipMemcpyHostToDevice, st));
@@ -632,14 +674,18 @@ int create_impl(const sph_scene_desc* d, sph_scene* s) {
   }
   HIP_TRY(hipMemcpyAsync(s->bodies, bodies.data(), sizeof(Body) * bodies.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(s->mat, mats.data(), sizeof(MatT<R>) * mats.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(s->matb, matb.data(), sizeof(double) * matb.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(s->dyn, dyn, sizeof(dyn), hipMemcpyHostToDevice, st));
   launch_fill_u32(s->err, 0u, 4, st);
+  launch_fill_u32(s->ps.ctr, 0u, 8, st);
+  if (P.pswitch) launch_fill_u32(s->ps.dirty, 0u, std::max(P.maxb, 1), st);
   zero_pairs(s, true);
   s->ip = 0;
   s->iu = 0;
   s->iT = 0;
   // body mass quantities, body-frame offsets, rigid particle velocities
   if (P.nb > 0) {
-    launch_mass_props_impl(s->bodies, s->s_x, s->s_m, s->s_rb, s->s_rk, P, nullptr, st);
+    launch_mass_props_impl(s->bodies, s->s_x, s->s_m, s->s_rb, s->s_rk, P, nullptr, nullptr, st);
     Launch<R>::rigid_velocity(cur<R>(s), P, st);
     launch_rigid_aw(s->bodies, P, s->s_body, s->s_rk, s->s_aw, st);
   }
@@ -653,6 +699,21 @@ int create_impl(const sph_scene_desc* d, sph_scene* s) {
   // the running pair total counts steps only
   launch_fill_u32(reinterpret_cast<uint32_t*>(s->pairs + 1), 0u, 2, st);
   HIP_TRY(hipStreamSynchronize(st));
+  return SPH_OK;
+}
+
+// rigid particles and bodies now (they change with phase switches)
+int dyn_counts(sph_scene* s, int64_t* n_rigid, int* n_bodies) {
+  if (!s->P.pswitch) {
+    *n_rigid = s->P.n_rigid;
+    *n_bodies = s->P.nb;
+    return SPH_OK;
+  }
+  uint32_t d[2];
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(hipMemcpy(d, s->dyn, sizeof(d), hipMemcpyDeviceToHost));
+  *n_rigid = d[0];
+  *n_bodies = (int)d[1];
   return SPH_OK;
 }
 
@@ -680,7 +741,10 @@ int read_particles_impl(sph_scene* s, uint32_t mask, double* out) {
   std::vector<int32_t> aux(n);
   std::vector<V4<R>> pos(n), u(n), a(n), uw(n);
   std::vector<R> rho(n), p(n), T(n), pw(n), m(n), dT(n);
-  std::vector<V4<double>> sf(std::max<int64_t>(P.n_rigid, 1));
+  int64_t nrig = 0;
+  int nbod = 0;
+  if (int e = dyn_counts(s, &nrig, &nbod)) return e;
+  std::vector<V4<double>> sf(std::max<int64_t>(nrig, 1));
   if (n > 0) {
     HIP_TRY(hipMemcpy(id.data(), s->id[s->ip], 4 * n, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(cell.data(), s->cell[s->ip], 4 * n, hipMemcpyDeviceToHost));
@@ -697,8 +761,7 @@ int read_particles_impl(sph_scene* s, uint32_t mask, double* out) {
     HIP_TRY(hipMemcpy(m.data(), s->m[s->ip], sizeof(R) * n, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(dT.data(), s->dTdt, sizeof(R) * n, hipMemcpyDeviceToHost));
   }
-  if (P.n_rigid > 0)
-    HIP_TRY(hipMemcpy(sf.data(), s->s_f, sizeof(V4<double>) * P.n_rigid, hipMemcpyDeviceToHost));
+  if (nrig > 0) HIP_TRY(hipMemcpy(sf.data(), s->s_f, sizeof(V4<double>) * nrig, hipMemcpyDeviceToHost));
   double* o = out;
   auto vec = [&](auto getter) {
     for (int64_t i = 0; i < n; ++i) {
@@ -922,7 +985,9 @@ int sph_scene_read_particles(sph_scene* s, uint32_t field_mask, double* out_host
 int sph_scene_read_bodies(sph_scene* s, double* out_host, int32_t cap, int32_t* n_bodies) {
   if (check_state(s)) return SPH_E_INVALID;
   HIP_TRY(hipStreamSynchronize(s->stream));
-  const int nb = s->P.nb;
+  int64_t nrig = 0;
+  int nb = 0;
+  if (int e = dyn_counts(s, &nrig, &nb)) return e;
   if (n_bodies) *n_bodies = nb;
   if (!out_host || nb == 0) return SPH_OK;
   std::vector<Body> b(nb);
@@ -1021,16 +1086,19 @@ int sph_scene_read_stats(sph_scene* s, sph_stats* o) {
   HIP_TRY(hipMemcpy(pr, s->pairs, sizeof(pr), hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(&err, s->err, 4, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(g, s->gout, sizeof(g), hipMemcpyDeviceToHost));
+  int64_t nrig = 0;
+  int nbod = 0;
+  if (int e = dyn_counts(s, &nrig, &nbod)) return e;
   o->step = s->step;
   o->t = (double)s->step * P.dt;
   o->dt = P.dt;
   o->k_c = P.kc;
   o->d_c = P.dc;
   o->n = P.n;
-  o->n_fluid = s->n_fluid;
+  o->n_fluid = P.n - s->n_wall - nrig;
   o->n_wall = s->n_wall;
-  o->n_rigid = P.n_rigid;
-  o->n_bodies = P.nb;
+  o->n_rigid = nrig;
+  o->n_bodies = nbod;
   for (int a = 0; a < 3; ++a) o->grid[a] = P.nc[a];
   o->pairs_last = (int64_t)pr[0];
   o->pairs_total = (int64_t)pr[1];
@@ -1040,9 +1108,9 @@ int sph_scene_read_stats(sph_scene* s, sph_stats* o) {
   o->device_error = err;
   // fluid part from the device reduction, bodies added here
   double mass = g[0], mom[3] = {g[1], g[2], g[3]}, ke = g[4];
-  if (P.nb > 0) {
-    std::vector<Body> b(P.nb);
-    HIP_TRY(hipMemcpy(b.data(), s->bodies, sizeof(Body) * P.nb, hipMemcpyDeviceToHost));
+  if (nbod > 0) {
+    std::vector<Body> b(nbod);
+    HIP_TRY(hipMemcpy(b.data(), s->bodies, sizeof(Body) * nbod, hipMemcpyDeviceToHost));
     for (const Body& B : b) {
       if (!B.active) continue;
       mass += B.m;

@@ -65,6 +65,8 @@ struct Params {
   int n_mat, nb, maxb;
   int64_t n_rigid, n_moving;
   int64_t nrows, max_waves;
+  int64_t slot_cap;     // rigid slot capacity (all particles when phases switch)
+  int body_launch;      // bodies covered by body kernels (capacity when phases switch)
 };
 
 // one wavefront of the sweeps: up to 64 consecutive sorted particles of one
@@ -91,6 +93,30 @@ template <typename R>
 struct KC {
   R h, inv_h, wnorm, dnorm, rc2, L, dx, dx2, vol0, kc, dc, dt, hdt;
   R lo[3];
+};
+
+// device buffers of the phase switch
+struct PhaseBufs {
+  uint8_t* flag;                // per particle: 1 melts, 2 solidifies
+  int32_t* target;              // per particle: body a solidifying particle joins
+  uint32_t* label;              // per particle: component label (an original id)
+  uint32_t* body_of_id;         // per original id: new body of a component root
+  uint32_t* list;               // solidifying particles without a rigid neighbour
+  uint32_t* roots;              // component roots
+  uint32_t* ctr;                // [0] flagged, [1] queued, [2] joiners, [3] old slots, [6] sorted buffer
+  uint32_t* dirty;              // per body: 1 changed, 2 new
+  V4<double>* rold;             // per body: centre of mass before the switch
+  uint32_t* alive;              // per old slot: still rigid
+  uint32_t* alive_sc;           // exclusive scan of alive (slot capacity + 1)
+  uint32_t* bsum;               // scan scratch
+  unsigned long long* jkey[2];  // joiners: (body << 32 | original id), ping-pong
+  uint32_t* jidx[2];            // joiners: sorted particle index, ping-pong
+  uint32_t* snew;               // new slots: particle
+  int32_t* sbody;               // new slots: body
+  uint32_t* sid;                // new slots: original id
+  V4<double>* srb;              // new slots: body-frame offset (kept for survivors)
+  V4<double>* srk;              // new slots: world-frame offset (kept for survivors)
+  V4<double>* srf;              // new slots: particle force of the last evaluation (survivors)
 };
 
 // device pointers of one scene
@@ -140,6 +166,8 @@ struct View {
   uint32_t* err;
   unsigned long long* pairs;   // [0] last evaluation, [1] running total, [2..4] by target kind
   Lists nb;
+  uint32_t* dyn;               // [0] rigid particles, [1] bodies (change with phase switches)
+  PhaseBufs ps;
 };
 
 struct SortBufs {
@@ -168,19 +196,23 @@ struct Launch {
   static void nb_count(const View<R>& v, const Params& P, const KC<R>& k, uint32_t* cnt, hipStream_t st);
   static void nb_fill(const View<R>& v, const Params& P, const KC<R>& k, const uint64_t* off, uint32_t* ids, hipStream_t st);
   static void slot_positions(const View<R>& v, const Params& P, hipStream_t st);
-  static void phase_flags(const View<R>& v, const Params& P, uint32_t* flags, uint32_t* counter, hipStream_t st);
+  static void phase_switch(const View<R>& v, const Params& P, const KC<R>& k, const double* matb, hipStream_t st);
 };
 
 // precision-independent launchers
 void launch_fill_u32(uint32_t* p, uint32_t val, int64_t n, hipStream_t st);
-void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum, hipStream_t st);
+// gate (may be NULL): the scan is skipped when gate[0] == 0
+void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum, hipStream_t st,
+                     const uint32_t* gate = nullptr);
 void launch_wave_table(const Params& P, const uint32_t* cstart, uint32_t* wcount, uint32_t* woff, uint32_t* bsum,
                        WaveInfo* table, hipStream_t st);
 void launch_sort_keys(const Params& P, SortBufs sb, uint32_t* cstart, const uint32_t* id, hipStream_t st);
-void launch_body_kick_drift(Body* b, const Params& P, hipStream_t st);
+// nbd (may be NULL): device-side body count, else P.body_launch bodies
+void launch_body_kick_drift(Body* b, const Params& P, const uint32_t* nbd, hipStream_t st);
 void launch_mass_props_impl(Body* b, const V4<double>* s_x, const double* s_m, V4<double>* s_rb, V4<double>* s_rk,
-                            const Params& P, const uint32_t* only, hipStream_t st);
-void launch_body_reduce(Body* b, const V4<double>* s_f, const V4<double>* s_rk, const Params& P, int kick, hipStream_t st);
+                            const Params& P, const uint32_t* only, const uint32_t* nbd, hipStream_t st);
+void launch_body_reduce(Body* b, const V4<double>* s_f, const V4<double>* s_rk, const Params& P, int kick,
+                        const uint32_t* nbd, hipStream_t st);
 void launch_rigid_aw(Body* b, const Params& P, const int32_t* s_body, const V4<double>* s_rk, V4<double>* s_aw, hipStream_t st);
 
 }  // namespace sphrb

@@ -941,7 +941,7 @@ __global__ void __launch_bounds__(256) k_kick_drift(View<R> v, Params P, KC<R> k
 template <typename R>
 __global__ void __launch_bounds__(256) k_rigid_pose(View<R> v, Params P, uint32_t* key) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= P.n_rigid) return;
+  if (s >= (P.pswitch ? (int64_t)v.dyn[0] : P.n_rigid)) return;
   const int kb = v.s_body[s];
   const Body& B = v.bodies[kb];
   const int64_t i = v.s_sorted[s];
@@ -1006,9 +1006,10 @@ __global__ void __launch_bounds__(256) k_wall_motion(View<R> v, Params P, uint32
 
 // u_r = u_k + w_k x r_rk (second kick of rigid particles)
 template <typename R>
-__global__ void __launch_bounds__(256) k_rigid_velocity(View<R> v, Params P) {
+__global__ void __launch_bounds__(256) k_rigid_velocity(View<R> v, Params P, const uint32_t* gate) {
+  if (gate && gate[0] == 0u) return;
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= P.n_rigid) return;
+  if (s >= (P.pswitch ? (int64_t)v.dyn[0] : P.n_rigid)) return;
   const Body& B = v.bodies[v.s_body[s]];
   const V4<double> rk = v.s_rk[s];
   const double r[3] = {rk.x, rk.y, rk.z};
@@ -1024,9 +1025,10 @@ __global__ void __launch_bounds__(256) k_rigid_velocity(View<R> v, Params P) {
 
 // FP64 positions of rigid slots (for the mass quantities)
 template <typename R>
-__global__ void __launch_bounds__(256) k_slot_positions(View<R> v, Params P) {
+__global__ void __launch_bounds__(256) k_slot_positions(View<R> v, Params P, const uint32_t* gate) {
+  if (gate && gate[0] == 0u) return;
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= P.n_rigid) return;
+  if (s >= (P.pswitch ? (int64_t)v.dyn[0] : P.n_rigid)) return;
   const int64_t i = v.s_sorted[s];
   double x[3];
   get_pos<R>(P, v, i, x);
@@ -1071,7 +1073,9 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* t
   return base + inc - x;
 }
 
-__global__ void __launch_bounds__(256) k_scan_blocks(const uint32_t* in, uint32_t* out, uint32_t* bsum, int64_t n) {
+__global__ void __launch_bounds__(256) k_scan_blocks(const uint32_t* in, uint32_t* out, uint32_t* bsum, int64_t n,
+                                                     const uint32_t* gate) {
+  if (gate && gate[0] == 0u) return;
   const int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x * 4;
   uint32_t v[4], s = 0;
   for (int q = 0; q < 4; ++q) {
@@ -1087,7 +1091,9 @@ __global__ void __launch_bounds__(256) k_scan_blocks(const uint32_t* in, uint32_
   if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-__global__ void __launch_bounds__(256) k_scan_bsum(uint32_t* bsum, int64_t nb, uint32_t* out_total) {
+__global__ void __launch_bounds__(256) k_scan_bsum(uint32_t* bsum, int64_t nb, uint32_t* out_total,
+                                                   const uint32_t* gate) {
+  if (gate && gate[0] == 0u) return;
   __shared__ uint32_t carry;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
@@ -1105,7 +1111,9 @@ __global__ void __launch_bounds__(256) k_scan_bsum(uint32_t* bsum, int64_t nb, u
   if (threadIdx.x == 0) *out_total = carry;
 }
 
-__global__ void __launch_bounds__(256) k_scan_add(uint32_t* out, const uint32_t* bsum, int64_t n) {
+__global__ void __launch_bounds__(256) k_scan_add(uint32_t* out, const uint32_t* bsum, int64_t n,
+                                                  const uint32_t* gate) {
+  if (gate && gate[0] == 0u) return;
   const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x * 4;
   const uint32_t add = bsum[blockIdx.x];
   for (int q = 0; q < 4; ++q)
@@ -1241,8 +1249,10 @@ __device__ void body_accel(Body& B, int dim) {
 // particles in double-double, the wavefront and then the workgroup combine
 // the partial sums; lane 0 forms the accelerations and the second kick.
 __global__ void __launch_bounds__(256) k_body_reduce(Body* bodies, const V4<double>* s_f, const V4<double>* s_rk,
-                                                     int dim, double hdt, int kick) {
-  Body& B = bodies[blockIdx.x];
+                                                     int dim, double hdt, int kick, int nbh, const uint32_t* nbd) {
+  const int nb = nbd ? (int)*nbd : nbh;
+  for (int kb = blockIdx.x; kb < nb; kb += gridDim.x) {
+  Body& B = bodies[kb];
   DD acc[6];
   for (int q = 0; q < 6; ++q) { acc[q].hi = 0.0; acc[q].lo = 0.0; }
   const int s0 = B.slot0, ns = B.active ? B.nslot : 0;
@@ -1274,12 +1284,14 @@ __global__ void __launch_bounds__(256) k_body_reduce(Body* bodies, const V4<doub
       }
     }
   }
+  }
 }
 
 // first kick, drift and orientation update of every body
-__global__ void __launch_bounds__(64) k_body_kick_drift(Body* bodies, int nb, double dt, double hdt) {
+__global__ void __launch_bounds__(64) k_body_kick_drift(Body* bodies, int nbh, const uint32_t* nbd, double dt,
+                                                        double hdt) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nb) return;
+  if (k >= (nbd ? (int)*nbd : nbh)) return;
   Body& B = bodies[k];
   if (!B.active || B.fixed) return;
   for (int a = 0; a < 3; ++a) {
@@ -1311,13 +1323,22 @@ __global__ void __launch_bounds__(64) k_body_kick_drift(Body* bodies, int nb, do
 // body-frame offsets r^b = R^T (x_r - r_k).
 __global__ void __launch_bounds__(256) k_mass_props(Body* bodies, const V4<double>* s_x, const double* s_m,
                                                     V4<double>* s_rb, V4<double>* s_rk, int dim, double Ir_fac,
-                                                    const uint32_t* only) {
-  const int kb = blockIdx.x;
-  if (only && !only[kb]) return;
-  Body& B = bodies[kb];
-  const int s0 = B.slot0, ns = B.nslot;
+                                                    const uint32_t* only, int nbh, const uint32_t* nbd,
+                                                    const uint32_t* gate) {
+  if (gate && gate[0] == 0u) return;
   __shared__ double shm[4], shr[4][3], shI[4][6];
   __shared__ double gr[3];
+  const int nb = nbd ? (int)*nbd : nbh;
+  for (int kb = blockIdx.x; kb < nb; kb += gridDim.x) {
+  __syncthreads();
+  if (only && only[kb] == 0u) continue;
+  Body& B = bodies[kb];
+  const int s0 = B.slot0, ns = B.nslot;
+  if (ns == 0) {
+    // a body without particles keeps its last state and goes inactive
+    if (threadIdx.x == 0) B.active = 0;
+    continue;
+  }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   // partition: wavefront w takes slots w, w+4, ... in chunks of 64 lanes
   DD am, ax[3];
@@ -1424,6 +1445,7 @@ __global__ void __launch_bounds__(256) k_mass_props(Body* bodies, const V4<doubl
     o.x = rb[0]; o.y = rb[1]; o.z = rb[2];
     s_rb[s0 + q] = o;
   }
+  }
 }
 
 // acceleration of rigid particles as material points (used at set-up)
@@ -1492,11 +1514,12 @@ void launch_fill_u32(uint32_t* p, uint32_t val, int64_t n, hipStream_t st) {
   if (n > 0) k_fill_u32<<<nblk(n), 256, 0, st>>>(p, val, n);
 }
 
-void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum, hipStream_t st) {
+void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum, hipStream_t st,
+                     const uint32_t* gate) {
   const int64_t nb = (n + 1023) / 1024;
-  if (nb > 0) k_scan_blocks<<<(unsigned)nb, 256, 0, st>>>(in, out, bsum, n);
-  k_scan_bsum<<<1, 256, 0, st>>>(bsum, nb, out + n);
-  if (nb > 0) k_scan_add<<<(unsigned)nb, 256, 0, st>>>(out, bsum, n);
+  if (nb > 0) k_scan_blocks<<<(unsigned)nb, 256, 0, st>>>(in, out, bsum, n, gate);
+  k_scan_bsum<<<1, 256, 0, st>>>(bsum, nb, out + n, gate);
+  if (nb > 0) k_scan_add<<<(unsigned)nb, 256, 0, st>>>(out, bsum, n, gate);
 }
 
 void launch_wave_table(const Params& P, const uint32_t* cstart, uint32_t* wcount, uint32_t* woff, uint32_t* bsum,
@@ -1516,18 +1539,25 @@ void launch_sort_keys(const Params& P, SortBufs sb, uint32_t* cstart, const uint
   }
 }
 
-void launch_body_kick_drift(Body* b, const Params& P, hipStream_t st) {
-  if (P.nb > 0) k_body_kick_drift<<<nblk(P.nb, 64), 64, 0, st>>>(b, P.nb, P.dt, P.hdt);
+// body kernels loop over the bodies: up to 1024 workgroups
+static inline unsigned body_grid(const Params& P) { return (unsigned)std::min(P.body_launch, 1024); }
+
+void launch_body_kick_drift(Body* b, const Params& P, const uint32_t* nbd, hipStream_t st) {
+  if (P.body_launch > 0)
+    k_body_kick_drift<<<nblk(P.body_launch, 64), 64, 0, st>>>(b, P.body_launch, nbd, P.dt, P.hdt);
 }
 
 void launch_body_reduce(Body* b, const V4<double>* s_f, const V4<double>* s_rk, const Params& P, int kick,
-                        hipStream_t st) {
-  if (P.nb > 0) k_body_reduce<<<(unsigned)P.nb, 256, 0, st>>>(b, s_f, s_rk, P.dim, P.hdt, kick);
+                        const uint32_t* nbd, hipStream_t st) {
+  if (P.body_launch > 0)
+    k_body_reduce<<<body_grid(P), 256, 0, st>>>(b, s_f, s_rk, P.dim, P.hdt, kick, P.body_launch, nbd);
 }
 
 void launch_mass_props_impl(Body* b, const V4<double>* s_x, const double* s_m, V4<double>* s_rb, V4<double>* s_rk,
-                            const Params& P, const uint32_t* only, hipStream_t st) {
-  if (P.nb > 0) k_mass_props<<<(unsigned)P.nb, 256, 0, st>>>(b, s_x, s_m, s_rb, s_rk, P.dim, P.Ir_fac, only);
+                            const Params& P, const uint32_t* only, const uint32_t* nbd, hipStream_t st) {
+  if (P.body_launch > 0)
+    k_mass_props<<<body_grid(P), 256, 0, st>>>(b, s_x, s_m, s_rb, s_rk, P.dim, P.Ir_fac, only, P.body_launch, nbd,
+                                              nullptr);
 }
 
 void launch_rigid_aw(Body* b, const Params& P, const int32_t* s_body, const V4<double>* s_rk, V4<double>* s_aw,
@@ -1541,7 +1571,7 @@ void Launch<R>::kick_drift(const View<R>& v, const Params& P, const KC<R>& k, So
 }
 template <typename R>
 void Launch<R>::rigid_pose(const View<R>& v, const Params& P, const KC<R>&, SortBufs sb, double, hipStream_t st) {
-  if (P.n_rigid > 0) k_rigid_pose<R><<<nblk(P.n_rigid), 256, 0, st>>>(v, P, sb.key);
+  if (P.slot_cap > 0) k_rigid_pose<R><<<nblk(P.slot_cap), 256, 0, st>>>(v, P, sb.key);
 }
 template <typename R>
 void Launch<R>::wall_motion(const View<R>& v, const Params& P, const KC<R>&, SortBufs sb, double t, hipStream_t st) {
@@ -1582,7 +1612,7 @@ void Launch<R>::forces(const View<R>& v, const Params& P, const KC<R>& k, int ki
 }
 template <typename R>
 void Launch<R>::rigid_velocity(const View<R>& v, const Params& P, hipStream_t st) {
-  if (P.n_rigid > 0) k_rigid_velocity<R><<<nblk(P.n_rigid), 256, 0, st>>>(v, P);
+  if (P.slot_cap > 0) k_rigid_velocity<R><<<nblk(P.slot_cap), 256, 0, st>>>(v, P, nullptr);
 }
 template <typename R>
 void Launch<R>::global_sums(const View<R>& v, const Params& P, double* partials, int nblocks, double* out,
@@ -1605,10 +1635,471 @@ void Launch<R>::nb_fill(const View<R>& v, const Params& P, const KC<R>&, const u
 }
 template <typename R>
 void Launch<R>::slot_positions(const View<R>& v, const Params& P, hipStream_t st) {
-  if (P.n_rigid > 0) k_slot_positions<R><<<nblk(P.n_rigid), 256, 0, st>>>(v, P);
+  if (P.slot_cap > 0) k_slot_positions<R><<<nblk(P.slot_cap), 256, 0, st>>>(v, P, nullptr);
 }
+
+// ---------------------------------------------------------------------------
+// reversible phase transition (Sec. "Modeling thermally driven reversible
+// phase transitions")
+//
+// Enqueued after every step when enabled.  Apart from the flag pass, every
+// kernel returns at once unless some particle crossed its transition
+// temperature, so a step without a switch costs one pass over the
+// particles.  Readings: strict comparisons, phases without a partner never
+// switch; melting first, then every solidifying particle joins the body of
+// its nearest rigid neighbour within r_c (ties: lower body id, then lower
+// original id); the remaining solidifying particles form one new body per
+// connected component (pairs closer than r_c), numbered in ascending order
+// of the component's smallest original id; bodies that changed get new mass
+// quantities and offsets, and their velocity follows rigid body motion with
+// unchanged angular velocity.  Rigid slots stay ordered by (body, original
+// id): the surviving slots keep that order, the joining particles are
+// sorted by the same key and the two sequences are merged.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void wave_count(uint32_t* ctr, bool pred) {
+  const unsigned long long m = __ballot(pred);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(ctr, (uint32_t)__popcll(m));
+}
+
+__device__ __forceinline__ unsigned long long slot_key(int body, uint32_t id) {
+  return ((unsigned long long)(uint32_t)body << 32) | (unsigned long long)id;
+}
+
+// first index in [0, n) whose key is not below x
+__device__ __forceinline__ uint32_t lower_bound_u64(const unsigned long long* a, uint32_t n, unsigned long long x) {
+  uint32_t lo = 0u, hi = n;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1u;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// the wave holding sorted particle i (waves are in ascending p0 order)
 template <typename R>
-void Launch<R>::phase_flags(const View<R>&, const Params&, uint32_t*, uint32_t*, hipStream_t) {}
+__device__ __forceinline__ uint32_t wave_of(const View<R>& v, uint32_t i) {
+  uint32_t lo = 0u, hi = *v.nb.nwaves;
+  while (hi - lo > 1u) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (v.nb.table[mid].p0 <= i) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(64) k_ps_begin(View<R> v) {
+  if (threadIdx.x < 8) v.ps.ctr[threadIdx.x] = threadIdx.x == 3 ? v.dyn[0] : 0u;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_ps_flags(View<R> v, Params P) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool any = false;
+  if (i < P.n) {
+    const uint32_t inf = v.info[i];
+    const uint32_t kind = ikind(inf);
+    const MatT<R>& M = v.mat[iphase(inf)];
+    uint8_t f = 0;
+    if (M.switch_to >= 0) {
+      const R T = v.T[i];
+      if (kind == KR && T > M.T_t) f = 1;
+      else if (kind == KF && T < M.T_t) f = 2;
+    }
+    v.ps.flag[i] = f;
+    any = f != 0;
+  }
+  wave_count(&v.ps.ctr[0], any);
+}
+
+// melting: the particle keeps the velocity and the acceleration of its
+// material point, a_k + alpha_k x r_rk + omega_k x (omega_k x r_rk)
+template <typename R>
+__global__ void __launch_bounds__(256) k_ps_melt(View<R> v, Params P) {
+  if (v.ps.ctr[0] == 0u) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.n || v.ps.flag[i] != 1) return;
+  const uint32_t inf = v.info[i];
+  const int32_t s = v.aux[i];
+  const int kb = v.s_body[s];
+  const Body& B = v.bodies[kb];
+  const V4<double> r4 = v.s_rk[s];
+  const double rk[3] = {r4.x, r4.y, r4.z};
+  double t1[3], t2[3], t3[3];
+  cross3(B.al, rk, t1);
+  cross3(B.w, rk, t2);
+  cross3(B.w, t2, t3);
+  V4<R> a;
+  a.x = (R)(B.a[0] + t1[0] + t3[0]);
+  a.y = (R)(B.a[1] + t1[1] + t3[1]);
+  a.z = P.dim == 3 ? (R)(B.a[2] + t1[2] + t3[2]) : R(0);
+  a.w = R(0);
+  v.a[i] = a;
+  v.info[i] = mkinfo(KF, (uint32_t)v.mat[iphase(inf)].switch_to, 0u, -1);
+  v.aux[i] = -1;
+  v.ps.dirty[kb] = 1u;
+}
+
+// nearest rigid neighbour of every solidifying particle, from its list;
+// particles without one are queued for the component search
+template <typename R, int DIM>
+__global__ void __launch_bounds__(64) k_ps_nearest(View<R> v, Params P, KC<R> k) {
+  constexpr int CAP = Nb<DIM>::cap, NR = Nb<DIM>::rows;
+  if (v.ps.ctr[0] == 0u) return;
+  const int w = blockIdx.x;
+  if (w >= (int)*v.nb.nwaves) return;
+  const WaveInfo wi = v.nb.table[w];
+  const int lane = threadIdx.x;
+  if (lane >= (int)wi.cnt) return;
+  const uint32_t i = wi.p0 + (uint32_t)lane;
+  if (v.ps.flag[i] != 2) return;
+  const WaveGeo g = wave_geo<R>(v, P, wi);
+  const V4<R> T = to_frame<R>(v.pos[i], k, g.cx_first, 0, 0);
+  const uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + lane;
+  bool found = false;
+  R br2 = R(0);
+  int bb = 0;
+  uint32_t bid = 0u;
+  for (int rr = 0; rr < NR; ++rr) {
+    const int dz = DIM == 3 ? rr / 3 - 1 : 0, dy = rr % 3 - 1;
+    const int tb = v.nb.rbase[(size_t)w * NR + rr];
+    const int c = v.nb.rcnt[((size_t)w * NR + rr) * 64 + lane];
+    const uint32_t jlo = v.nb.jlo[(size_t)w * NR + rr];
+    for (int t = 0; t < c; ++t) {
+      const uint32_t j = jlo + ((uint32_t)gl[(size_t)(tb + t) * 64] & 0xfffu);
+      if (j == i) continue;
+      const uint32_t ij = v.info[j];
+      if (ikind(ij) != KR) continue;
+      R d0, d1, d2;
+      const R r2 = dist2<R, DIM>(T, to_frame<R>(v.pos[j], k, g.cx_first, dy, dz), d0, d1, d2);
+      const int bj = ibody(ij);
+      const uint32_t idj = v.id[j];
+      if (!found || r2 < br2 || (r2 == br2 && (bj < bb || (bj == bb && idj < bid)))) {
+        found = true;
+        br2 = r2;
+        bb = bj;
+        bid = idj;
+      }
+    }
+  }
+  if (found) {
+    v.ps.target[i] = bb;
+  } else {
+    v.ps.target[i] = -1;
+    v.ps.label[i] = v.id[i];
+    v.ps.list[atomicAdd(&v.ps.ctr[1], 1u)] = i;
+  }
+}
+
+// Connected components of the queued particles and their new bodies, in one
+// workgroup: every particle's label (an original id) drops to the smallest
+// label among its queued neighbours until no label changes, which leaves
+// the smallest original id of the component.
+template <typename R, int DIM>
+__global__ void __launch_bounds__(256) k_ps_components(View<R> v, Params P, const double* matb) {
+  constexpr int CAP = Nb<DIM>::cap, NR = Nb<DIM>::rows;
+  const uint32_t nu = v.ps.ctr[1];
+  if (nu == 0u) return;
+  __shared__ uint32_t nroot, changed;
+  if (threadIdx.x == 0) nroot = 0u;
+  for (;;) {
+    if (threadIdx.x == 0) changed = 0u;
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < nu; q += blockDim.x) {
+      const uint32_t i = v.ps.list[q];
+      const uint32_t w = wave_of<R>(v, i);
+      const int lane = (int)(i - v.nb.table[w].p0);
+      const uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + lane;
+      uint32_t m = v.ps.label[i];
+      for (int rr = 0; rr < NR; ++rr) {
+        const int tb = v.nb.rbase[(size_t)w * NR + rr];
+        const int c = v.nb.rcnt[((size_t)w * NR + rr) * 64 + lane];
+        const uint32_t jlo = v.nb.jlo[(size_t)w * NR + rr];
+        for (int t = 0; t < c; ++t) {
+          const uint32_t j = jlo + ((uint32_t)gl[(size_t)(tb + t) * 64] & 0xfffu);
+          if (j == i || v.ps.flag[j] != 2 || v.ps.target[j] >= 0) continue;
+          const uint32_t lj = v.ps.label[j];
+          if (lj < m) m = lj;
+        }
+      }
+      if (m < v.ps.label[i]) {
+        v.ps.label[i] = m;
+        changed = 1u;
+      }
+    }
+    __syncthreads();
+    const uint32_t c = changed;
+    __syncthreads();
+    if (c == 0u) break;
+  }
+  // roots, numbered by ascending original id after the existing bodies
+  for (uint32_t q = threadIdx.x; q < nu; q += blockDim.x) {
+    const uint32_t i = v.ps.list[q];
+    if (v.ps.label[i] == v.id[i]) v.ps.roots[atomicAdd(&nroot, 1u)] = i;
+  }
+  __syncthreads();
+  const uint32_t nr = nroot;
+  const uint32_t nb0 = v.dyn[1];
+  for (uint32_t q = threadIdx.x; q < nr; q += blockDim.x) {
+    const uint32_t i = v.ps.roots[q];
+    const uint32_t my = v.id[i];
+    uint32_t rank = 0u;
+    for (uint32_t o = 0; o < nr; ++o) rank += v.id[v.ps.roots[o]] < my ? 1u : 0u;
+    const uint32_t kb = nb0 + rank;
+    if (kb >= (uint32_t)P.maxb) {
+      set_err(v.err, ERR_BODYCAP);
+      v.ps.body_of_id[my] = 0xffffffffu;
+      continue;
+    }
+    v.ps.body_of_id[my] = kb;
+    Body& B = v.bodies[kb];
+    B.q[0] = 1.0; B.q[1] = 0.0; B.q[2] = 0.0; B.q[3] = 0.0;
+    const int ps = v.mat[iphase(v.info[i])].switch_to;
+    for (int a = 0; a < 3; ++a) {
+      B.w[a] = 0.0;
+      B.al[a] = 0.0;
+      B.f[a] = 0.0;
+      B.t[a] = 0.0;
+      B.b[a] = a < P.dim ? matb[3 * ps + a] : 0.0;
+    }
+    B.fixed = 0;
+    B.active = 1;
+    v.ps.dirty[kb] = 2u;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t nbn = nb0 + nr;
+    v.dyn[1] = nbn < (uint32_t)P.maxb ? nbn : (uint32_t)P.maxb;
+  }
+  for (uint32_t q = threadIdx.x; q < nu; q += blockDim.x) {
+    const uint32_t i = v.ps.list[q];
+    const uint32_t kb = v.ps.body_of_id[v.ps.label[i]];
+    v.ps.target[i] = kb == 0xffffffffu ? -1 : (int32_t)kb;
+  }
+}
+
+// solidification: kind, phase and body; the joining particles are queued
+// with their slot key
+template <typename R>
+__global__ void __launch_bounds__(256) k_ps_apply(View<R> v, Params P) {
+  if (v.ps.ctr[0] == 0u) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.n || v.ps.flag[i] != 2) return;
+  const int32_t t = v.ps.target[i];
+  if (t < 0) return;
+  const uint32_t inf = v.info[i];
+  v.info[i] = mkinfo(KR, (uint32_t)v.mat[iphase(inf)].switch_to, 0u, t);
+  if (v.ps.dirty[t] == 0u) v.ps.dirty[t] = 1u;
+  const uint32_t q = atomicAdd(&v.ps.ctr[2], 1u);
+  v.ps.jkey[0][q] = slot_key(t, v.id[i]);
+  v.ps.jidx[0][q] = (uint32_t)i;
+}
+
+// old slots that stay rigid
+template <typename R>
+__global__ void __launch_bounds__(256) k_ps_alive(View<R> v, Params P) {
+  if (v.ps.ctr[0] == 0u) return;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= P.slot_cap) return;
+  const uint32_t nold = v.ps.ctr[3];
+  v.ps.alive[s] = (s < (int64_t)nold && ikind(v.info[v.s_sorted[s]]) == KR) ? 1u : 0u;
+}
+
+// bottom-up merge sort of the joiner keys in one workgroup (keys are
+// unique); the result ends in buffer ctr[6]
+__global__ void __launch_bounds__(256) k_ps_sort_joiners(PhaseBufs ps) {
+  const uint32_t nj = ps.ctr[2];
+  if (ps.ctr[0] == 0u || nj == 0u) return;
+  int cur = 0;
+  for (uint32_t w = 1u; w < nj; w <<= 1) {
+    const unsigned long long* ka = ps.jkey[cur];
+    const uint32_t* ia = ps.jidx[cur];
+    unsigned long long* kb = ps.jkey[1 - cur];
+    uint32_t* ib = ps.jidx[1 - cur];
+    for (uint32_t e = threadIdx.x; e < nj; e += blockDim.x) {
+      const uint32_t start = e / (2u * w) * (2u * w);
+      const uint32_t mid = start + w < nj ? start + w : nj;
+      const uint32_t end = start + 2u * w < nj ? start + 2u * w : nj;
+      const unsigned long long key = ka[e];
+      uint32_t pos;
+      if (e < mid) pos = (e - start) + lower_bound_u64(ka + mid, end - mid, key);
+      else pos = (e - mid) + lower_bound_u64(ka + start, mid - start, key);
+      kb[start + pos] = key;
+      ib[start + pos] = ia[e];
+    }
+    __syncthreads();
+    cur = 1 - cur;
+  }
+  if (threadIdx.x == 0) ps.ctr[6] = (uint32_t)cur;
+}
+
+// merge of the surviving slots (already in key order) with the sorted
+// joiners into the new slot order
+template <typename R>
+__global__ void __launch_bounds__(256) k_ps_place(View<R> v, Params P) {
+  if (v.ps.ctr[0] == 0u) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t nold = v.ps.ctr[3], nj = v.ps.ctr[2];
+  const unsigned long long* jk = v.ps.jkey[v.ps.ctr[6]];
+  const uint32_t* ji = v.ps.jidx[v.ps.ctr[6]];
+  if (t < (int64_t)nold && v.ps.alive[t]) {
+    const unsigned long long key = slot_key(v.s_body[t], v.s_id[t]);
+    const uint32_t pos = v.ps.alive_sc[t] + lower_bound_u64(jk, nj, key);
+    v.ps.snew[pos] = (uint32_t)v.s_sorted[t];
+    v.ps.sbody[pos] = v.s_body[t];
+    v.ps.sid[pos] = v.s_id[t];
+    v.ps.srb[pos] = v.s_rb[t];
+    v.ps.srk[pos] = v.s_rk[t];
+    v.ps.srf[pos] = v.s_f[t];
+  }
+  if (t < (int64_t)nj) {
+    const unsigned long long key = jk[t];
+    // old slots below the key (dead ones included), then the live ones among them
+    uint32_t lo = 0u, hi = nold;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (slot_key(v.s_body[mid], v.s_id[mid]) < key) lo = mid + 1u;
+      else hi = mid;
+    }
+    const uint32_t pos = (uint32_t)t + v.ps.alive_sc[lo];
+    V4<double> z;
+    z.x = z.y = z.z = z.w = 0.0;
+    v.ps.snew[pos] = ji[t];
+    v.ps.sbody[pos] = (int32_t)(key >> 32);
+    v.ps.sid[pos] = (uint32_t)(key & 0xffffffffull);
+    v.ps.srb[pos] = z;
+    v.ps.srk[pos] = z;
+    v.ps.srf[pos] = z;
+  }
+}
+
+// every body's old centre of mass; slot ranges cleared
+template <typename R>
+__global__ void __launch_bounds__(256) k_ps_bodies(View<R> v, Params P) {
+  if (v.ps.ctr[0] == 0u) return;
+  const uint32_t nb = v.dyn[1];
+  for (uint32_t kb = blockIdx.x * blockDim.x + threadIdx.x; kb < nb; kb += gridDim.x * blockDim.x) {
+    Body& B = v.bodies[kb];
+    V4<double> r;
+    r.x = B.r[0]; r.y = B.r[1]; r.z = B.r[2]; r.w = 0.0;
+    v.ps.rold[kb] = r;
+    B.nslot = 0;
+  }
+}
+
+// new slot arrays, body slot ranges (first slot), rigid count
+template <typename R>
+__global__ void __launch_bounds__(256) k_ps_slots(View<R> v, Params P) {
+  if (v.ps.ctr[0] == 0u) return;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t total = v.ps.alive_sc[v.ps.ctr[3]] + v.ps.ctr[2];
+  if (s == 0) v.dyn[0] = total;
+  if (s >= (int64_t)total) return;
+  const uint32_t i = v.ps.snew[s];
+  const int kb = v.ps.sbody[s];
+  v.s_sorted[s] = (int32_t)i;
+  v.s_body[s] = kb;
+  v.s_id[s] = v.ps.sid[s];
+  v.s_rb[s] = v.ps.srb[s];
+  v.s_rk[s] = v.ps.srk[s];
+  v.s_f[s] = v.ps.srf[s];
+  v.aux[i] = (int32_t)s;
+  if (s == 0 || v.ps.sbody[s - 1] != kb) v.bodies[kb].slot0 = (int32_t)s;
+}
+
+// body slot ranges (count), after the first slots are known
+template <typename R>
+__global__ void __launch_bounds__(256) k_ps_slot_ends(View<R> v, Params P) {
+  if (v.ps.ctr[0] == 0u) return;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t total = v.dyn[0];
+  if (s >= (int64_t)total) return;
+  const int kb = v.ps.sbody[s];
+  if (s + 1 == (int64_t)total || v.ps.sbody[s + 1] != kb) v.bodies[kb].nslot = (int32_t)(s + 1) - v.bodies[kb].slot0;
+}
+
+// after the new mass quantities: velocity of changed bodies follows rigid
+// motion, u_k += omega_k x (r_k - r_k,old); new bodies take the
+// mass-weighted velocity and acceleration of their particles
+template <typename R>
+__global__ void __launch_bounds__(256) k_ps_fix(View<R> v, Params P) {
+  if (v.ps.ctr[0] == 0u) return;
+  const uint32_t nb = v.dyn[1];
+  for (uint32_t kb = blockIdx.x; kb < nb; kb += gridDim.x) {
+    const uint32_t d = v.ps.dirty[kb];
+    Body& B = v.bodies[kb];
+    const int act = B.active;
+    __syncthreads();
+    if (d == 0u) continue;
+    if (threadIdx.x == 0) v.ps.dirty[kb] = 0u;
+    if (!act) continue;
+    if (d == 1u) {
+      if (threadIdx.x == 0) {
+        const V4<double> ro = v.ps.rold[kb];
+        const double dr[3] = {B.r[0] - ro.x, B.r[1] - ro.y, B.r[2] - ro.z};
+        double wr[3];
+        cross3(B.w, dr, wr);
+        for (int a = 0; a < P.dim; ++a) B.u[a] = B.u[a] + wr[a];
+      }
+      continue;
+    }
+    DD acc[7];
+    for (int q = 0; q < 7; ++q) acc[q].hi = acc[q].lo = 0.0;
+    for (int q = threadIdx.x; q < B.nslot; q += blockDim.x) {
+      const int64_t i = v.s_sorted[B.slot0 + q];
+      const double m = (double)v.m[i];
+      const V4<R> u = v.u[i];
+      const V4<R> a = v.a[i];
+      dd_add(acc[0], m);
+      dd_add(acc[1], m * (double)u.x);
+      dd_add(acc[2], m * (double)u.y);
+      dd_add(acc[3], m * (double)u.z);
+      dd_add(acc[4], m * (double)a.x);
+      dd_add(acc[5], m * (double)a.y);
+      dd_add(acc[6], m * (double)a.z);
+    }
+    double o[7];
+    block_reduce_dd<7>(acc, o);
+    if (threadIdx.x == 0) {
+      for (int a = 0; a < 3; ++a) {
+        B.u[a] = a < P.dim ? o[1 + a] / o[0] : 0.0;
+        B.a[a] = a < P.dim ? o[4 + a] / o[0] : 0.0;
+      }
+    }
+  }
+}
+
+template <typename R>
+void Launch<R>::phase_switch(const View<R>& v, const Params& P, const KC<R>& k, const double* matb, hipStream_t st) {
+  if (P.n <= 0 || !P.pswitch) return;
+  const unsigned gn = nblk(P.n), gs = nblk(P.slot_cap);
+  const unsigned gb = (unsigned)std::min(std::max(P.maxb, 1), 1024);
+  k_ps_begin<R><<<1, 64, 0, st>>>(v);
+  k_ps_flags<R><<<gn, 256, 0, st>>>(v, P);
+  k_ps_melt<R><<<gn, 256, 0, st>>>(v, P);
+  if (P.dim == 2) {
+    k_ps_nearest<R, 2><<<(unsigned)P.max_waves, 64, 0, st>>>(v, P, k);
+    k_ps_components<R, 2><<<1, 256, 0, st>>>(v, P, matb);
+  } else {
+    k_ps_nearest<R, 3><<<(unsigned)P.max_waves, 64, 0, st>>>(v, P, k);
+    k_ps_components<R, 3><<<1, 256, 0, st>>>(v, P, matb);
+  }
+  k_ps_apply<R><<<gn, 256, 0, st>>>(v, P);
+  k_ps_alive<R><<<gs, 256, 0, st>>>(v, P);
+  launch_scan_u32(v.ps.alive, v.ps.alive_sc, P.slot_cap, v.ps.bsum, st, v.ps.ctr);
+  k_ps_sort_joiners<<<1, 256, 0, st>>>(v.ps);
+  k_ps_place<R><<<gs, 256, 0, st>>>(v, P);
+  k_ps_bodies<R><<<nblk(P.maxb), 256, 0, st>>>(v, P);
+  k_ps_slots<R><<<gs, 256, 0, st>>>(v, P);
+  k_ps_slot_ends<R><<<gs, 256, 0, st>>>(v, P);
+  k_slot_positions<R><<<gs, 256, 0, st>>>(v, P, v.ps.ctr);
+  k_mass_props<<<gb, 256, 0, st>>>(v.bodies, v.s_x, v.s_m, v.s_rb, v.s_rk, P.dim, P.Ir_fac, v.ps.dirty, P.maxb,
+                                   v.dyn + 1, v.ps.ctr);
+  k_ps_fix<R><<<gb, 256, 0, st>>>(v, P);
+  k_rigid_velocity<R><<<gs, 256, 0, st>>>(v, P, v.ps.ctr);
+}
 
 template struct Launch<float>;
 template struct Launch<double>;

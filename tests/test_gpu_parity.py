@@ -133,3 +133,116 @@ def test_fp32_gates(B, make):
     assert e["rho"] <= 1e-4, e
     eb = body_errors(sc, g.bodies(), o.bodies())
     assert eb["r"] <= 1e-3 and eb["m"] <= 1e-12, eb
+
+
+# ---- reversible phase transition -------------------------------------------
+
+def _scripted_switch_scene():
+    """The oracle's scripted switch scene: two rigid particles melt, one fluid
+    particle next to the disc joins it, two far fluid clusters form new
+    bodies; T exactly at T_t does not switch."""
+    from test_oracle_bodies import _switch_scene
+    sc = _switch_scene()
+    rigid = np.nonzero(sc.kind == S.RIGID)[0]
+    fl = np.nonzero(sc.kind == S.FLUID)[0]
+    sc.T[rigid[0]] = 70.0
+    sc.T[rigid[5]] = 50.0
+    sc.T[rigid[-1]] = 50.0 + 1e-9
+    dist = np.linalg.norm(sc.x[fl, :2] - np.array([0.4, 0.6]), axis=1)
+    sc.T[fl[np.argsort(dist)[0]]] = 40.0
+    for c in ((0.15, 0.15), (0.62, 0.15)):
+        sc.T[fl[np.linalg.norm(sc.x[fl, :2] - np.array(c), axis=1) < 0.06]] = 10.0
+    return sc
+
+
+def _run_switch_pair(B, sc, steps):
+    """Run both sides; also return the kinds before the last step."""
+    o, g = run_pair(sc, B.SPH_FP64, steps - 1)
+    prev = o.get_int(O.I_KIND)
+    o.step(1)
+    g.step(1)
+    g.sync()
+    return o, g, prev
+
+
+def _assert_switch_parity(sc, o, g, prev_kind):
+    """Structure bit for bit, fields and bodies within 1e-10.  The
+    per-evaluation wall/rigid diagnostics (p_w, u~_w, particle force) of a
+    particle that switched after the last evaluation are not defined on
+    either side and are left out."""
+    assert_bitwise_structure(o, g, sc)
+    kind = o.get_int(O.I_KIND)
+    gf, of = gpu_fields(g), oracle_fields(o)
+    sw = prev_kind != kind
+    for key in ("PW", "UW", "FR"):
+        gf[key][sw] = of[key][sw]
+    e = field_errors(sc, gf, of, kind)
+    assert max(e.values()) <= FP64_TOL, e
+    ob, gb = o.bodies(), g.bodies()
+    assert gb.shape == ob.shape
+    assert np.array_equal(gb[:, 32], ob[:, 32])          # active flags
+    act = ob[:, 32] > 0
+    eb = body_errors(sc, gb[act], ob[act])
+    assert max(eb.values()) <= FP64_TOL, eb
+    st = g.stats()
+    assert st.n_rigid == int(np.sum(kind == S.RIGID))
+    assert st.n_fluid == int(np.sum(kind == S.FLUID))
+    assert st.n_bodies == ob.shape[0]
+
+
+@pytest.mark.parametrize("steps", [1, 30])
+def test_phase_switch_scripted_fp64_parity(B, steps):
+    sc = _scripted_switch_scene()
+    o, g, prev = _run_switch_pair(B, sc, steps)
+    _assert_switch_parity(sc, o, g, prev)
+    assert o.bodies().shape[0] == 3
+
+
+def test_phase_switch_bulk_solidification_fp64_parity(B):
+    """Every fluid particle below T_t at once: the particles within r_c of
+    the disc join it, all others form new bodies in one switch (a large
+    joiner sort and component search)."""
+    from test_oracle_bodies import _switch_scene
+    sc = _switch_scene()
+    sc.T[sc.kind == S.FLUID] = 10.0
+    sc.max_bodies = 64
+    o, g, prev = _run_switch_pair(B, sc, 1)
+    _assert_switch_parity(sc, o, g, prev)
+    assert np.all(o.get_int(O.I_KIND)[sc.kind == S.FLUID] == S.RIGID)
+    o.step(4)
+    g.step(4)
+    prev = o.get_int(O.I_KIND)
+    o.step(1)
+    g.step(1)
+    g.sync()
+    _assert_switch_parity(sc, o, g, prev)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_phase_switch_thermal_fp64_parity(B, dim):
+    """Two-phase thermal scene with conduction and the moving heat source:
+    one grain heated above T_t melts entirely (its body goes inactive), part
+    of another melts; 40 steps with switching on every step."""
+    sc = S.config_c3(seed=2, nsites=(20, 14, 12), n_grains=4 if dim == 3 else 3, median_r=2.5, dim=dim)
+    rg = sc.kind == S.RIGID
+    bodies = np.unique(sc.body[rg])
+    assert bodies.size >= 2
+    sc.T[rg & (sc.body == bodies[0])] = 70.0
+    b1 = rg & (sc.body == bodies[1])
+    cut = np.median(sc.x[b1, 0])
+    sc.T[b1 & (sc.x[:, 0] < cut)] = 52.0
+    o, g, prev = _run_switch_pair(B, sc, 40)
+    _assert_switch_parity(sc, o, g, prev)
+    kind = o.get_int(O.I_KIND)
+    assert np.any(kind[rg] == S.FLUID)          # something melted
+
+
+def test_phase_switch_body_capacity_error(B):
+    """More new bodies than max_bodies: a sticky device error, reported by sync."""
+    sc = _scripted_switch_scene()
+    sc.max_bodies = 2
+    g = B.SphScene(sc, precision=B.SPH_FP64)
+    g.step(1)
+    with pytest.raises(RuntimeError):
+        g.sync()
+    assert g.stats().device_error & 16
