@@ -58,7 +58,24 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-side", type=int, default=100)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (calibrates HBM byte counters)")
     return ap.parse_args()
+
+
+def calibrate_copy(mib):
+    """A plain device-to-device copy of a known size, for scaling the
+    FETCH_SIZE / WRITE_SIZE counters of the same profiler run."""
+    import torch
+    n = mib * (1 << 20)
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": n, "launches": 5}), flush=True)
 
 
 def field_errors(sc, g, o, O, S):
@@ -90,6 +107,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     sc = S.config_c2(seed=args.seed, n_side=args.n_side)
     counts = sc.counts()
 

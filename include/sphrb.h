@@ -206,6 +206,27 @@ int sph_scene_read_stats(sph_scene *s, sph_stats *out_host);
 int sph_scene_enable_timers(sph_scene *s, int32_t enable);
 int sph_scene_read_timers(sph_scene *s, double *stage_ms, int64_t *steps, double *step_ms, int64_t cap);
 
+/* Checkpoint / resume.  A state image is a header (parameters, step
+ * count, buffer parities) followed by the scene's device arena verbatim, so
+ * a scene re-created from it continues bit for bit as the original would
+ * have (timers are not part of the state).
+ *   sph_scene_state_bytes: size of the image (0 for a NULL scene).
+ *   sph_scene_read_state: waits for the scene's stream and writes the image
+ *     into host_blob (at least sph_scene_state_bytes bytes, else
+ *     SPH_E_INVALID).
+ *   sph_state_arena_bytes: device arena size a scene re-created from the
+ *     image needs; 0 and *status = SPH_E_INVALID for an image that is not
+ *     one, was written by another ABI version or is truncated.
+ *   sph_scene_create_from_state: re-creates the scene in the caller's
+ *     256-byte aligned arena on the caller's stream (as sph_scene_create;
+ *     the image is read during the call only).  On error nothing is left
+ *     allocated and *out is NULL. */
+size_t sph_scene_state_bytes(sph_scene *s);
+int sph_scene_read_state(sph_scene *s, void *host_blob, size_t bytes);
+size_t sph_state_arena_bytes(const void *host_blob, size_t bytes, int *status);
+int sph_scene_create_from_state(const void *host_blob, size_t bytes, void *dev_arena, size_t arena_bytes,
+                                void *hip_stream, sph_scene **out);
+
 /* Release the scene's host-side handle.  Frees nothing the caller owns. */
 void sph_scene_destroy(sph_scene *s);
 

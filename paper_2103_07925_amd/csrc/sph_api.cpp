@@ -717,13 +717,38 @@ int dyn_counts(sph_scene* s, int64_t* n_rigid, int* n_bodies) {
   return SPH_OK;
 }
 
-size_t arena_for(const sph_scene_desc* d, const Params& P) {
+size_t arena_for_params(int precision, const Params& P) {
   sph_scene tmp;
   std::memset(&tmp, 0, sizeof(tmp));
   Carver cv{nullptr, 0};
-  if (d->precision == SPH_FP64) carve<double>(cv, &tmp, P, d->n_mat);
-  else carve<float>(cv, &tmp, P, d->n_mat);
+  if (precision == SPH_FP64) carve<double>(cv, &tmp, P, P.n_mat);
+  else carve<float>(cv, &tmp, P, P.n_mat);
   return align_up(cv.off);
+}
+
+size_t arena_for(const sph_scene_desc* d, const Params& P) { return arena_for_params(d->precision, P); }
+
+// State image: this header, then the scene's arena verbatim (the carve is a
+// function of the parameters only, so the image maps onto a new arena).
+struct StateHeader {
+  char magic[8];
+  int32_t abi, precision;
+  uint64_t arena_used;
+  int64_t step, n_fluid, n_wall;
+  int32_t ip, iu, iT, pad;
+  Params P;
+};
+constexpr char kStateMagic[8] = {'S', 'P', 'H', 'R', 'B', 'S', 'T', '1'};
+
+int parse_state(const void* blob, size_t bytes, StateHeader* h) {
+  if (!blob || bytes < sizeof(StateHeader)) return fail(SPH_E_INVALID, "state image too small");
+  std::memcpy(h, blob, sizeof(StateHeader));
+  if (std::memcmp(h->magic, kStateMagic, 8) != 0) return fail(SPH_E_INVALID, "not a scene state image");
+  if (h->abi != SPH_ABI_VERSION) return fail(SPH_E_INVALID, "state image of another ABI version");
+  if (h->precision != SPH_FP64 && h->precision != SPH_FP32_SWEEP) return fail(SPH_E_INVALID, "bad precision");
+  if (h->arena_used != arena_for_params(h->precision, h->P)) return fail(SPH_E_INVALID, "inconsistent state image");
+  if (bytes < sizeof(StateHeader) + h->arena_used) return fail(SPH_E_INVALID, "truncated state image");
+  return SPH_OK;
 }
 
 int check_state(sph_scene* s) {
@@ -1158,6 +1183,79 @@ int sph_scene_read_timers(sph_scene* s, double* stage_ms, int64_t* steps, double
   if (stage_ms)
     for (int g = 0; g < SPH_TIMER_STAGES; ++g) stage_ms[g] = sum[g];
   if (steps) *steps = nrec;
+  return SPH_OK;
+}
+
+size_t sph_scene_state_bytes(sph_scene* s) {
+  if (!s) return 0;
+  return sizeof(StateHeader) + arena_for_params(s->precision, s->P);
+}
+
+int sph_scene_read_state(sph_scene* s, void* host_blob, size_t bytes) {
+  if (check_state(s)) return SPH_E_INVALID;
+  const size_t used = arena_for_params(s->precision, s->P);
+  if (!host_blob || bytes < sizeof(StateHeader) + used) return fail(SPH_E_INVALID, "state buffer too small");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  StateHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, kStateMagic, 8);
+  h.abi = SPH_ABI_VERSION;
+  h.precision = s->precision;
+  h.arena_used = used;
+  h.step = s->step;
+  h.n_fluid = s->n_fluid;
+  h.n_wall = s->n_wall;
+  h.ip = s->ip;
+  h.iu = s->iu;
+  h.iT = s->iT;
+  h.P = s->P;
+  std::memcpy(host_blob, &h, sizeof(h));
+  HIP_TRY(hipMemcpy(static_cast<char*>(host_blob) + sizeof(h), s->arena, used, hipMemcpyDeviceToHost));
+  return SPH_OK;
+}
+
+size_t sph_state_arena_bytes(const void* host_blob, size_t bytes, int* status) {
+  StateHeader h;
+  const int st = parse_state(host_blob, bytes, &h);
+  if (status) *status = st;
+  return st == SPH_OK ? (size_t)h.arena_used : 0;
+}
+
+int sph_scene_create_from_state(const void* host_blob, size_t bytes, void* dev_arena, size_t arena_bytes,
+                                void* hip_stream, sph_scene** out) {
+  if (!out) return fail(SPH_E_INVALID, "null out");
+  *out = nullptr;
+  StateHeader h;
+  int st = parse_state(host_blob, bytes, &h);
+  if (st != SPH_OK) return st;
+  if (!dev_arena || arena_bytes < h.arena_used)
+    return fail(SPH_E_NOMEM, "arena needs " + std::to_string(h.arena_used) + " bytes");
+  if ((reinterpret_cast<uintptr_t>(dev_arena) & 255u) != 0) return fail(SPH_E_INVALID, "arena must be 256-byte aligned");
+  sph_scene* s = new (std::nothrow) sph_scene;
+  if (!s) return fail(SPH_E_NOMEM, "host allocation");
+  std::memset(s, 0, sizeof(*s));
+  s->P = h.P;
+  s->precision = h.precision;
+  s->stream = (hipStream_t)hip_stream;
+  s->arena = (char*)dev_arena;
+  s->arena_bytes = arena_bytes;
+  Carver cv{s->arena, 0};
+  if (h.precision == SPH_FP64) carve<double>(cv, s, s->P, s->P.n_mat);
+  else carve<float>(cv, s, s->P, s->P.n_mat);
+  s->step = h.step;
+  s->n_fluid = h.n_fluid;
+  s->n_wall = h.n_wall;
+  s->ip = h.ip;
+  s->iu = h.iu;
+  s->iT = h.iT;
+  hipError_t e = hipMemcpyAsync(s->arena, static_cast<const char*>(host_blob) + sizeof(StateHeader), h.arena_used,
+                                hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) {
+    delete s;
+    return fail(SPH_E_DEVICE, std::string("state upload: ") + hipGetErrorString(e));
+  }
+  *out = s;
   return SPH_OK;
 }
 

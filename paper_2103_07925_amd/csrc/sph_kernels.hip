@@ -225,11 +225,39 @@ __device__ __forceinline__ double info_to_r(uint32_t v, double) { return (double
 __device__ __forceinline__ uint32_t r_to_info(float v) { return __float_as_uint(v); }
 __device__ __forceinline__ uint32_t r_to_info(double v) { return (uint32_t)v; }
 
+// Per-phase constants the sweeps need for every neighbour, kept in LDS for
+// the first kMatLds phases (the rest are read from the global table).
+constexpr int kMatLds = 16;
+template <typename R>
+struct MatL {
+  R eta, kappa, rho0, p0, inv_p0, b0, b1, b2, dir;
+};
+template <typename R>
+__device__ __forceinline__ MatL<R> mat_from(const MatT<R>& M) {
+  MatL<R> o;
+  o.eta = M.eta; o.kappa = M.kappa; o.rho0 = M.rho0; o.p0 = M.p0; o.inv_p0 = M.inv_p0;
+  o.b0 = M.b[0]; o.b1 = M.b[1]; o.b2 = M.b[2]; o.dir = M.dirichlet ? R(1) : R(0);
+  return o;
+}
+// fills the table; every thread of the workgroup calls it (it synchronises)
+template <typename R>
+__device__ __forceinline__ void stage_mats(MatL<R>* sm, const View<R>& v, const Params& P) {
+  const int nm = P.n_mat < kMatLds ? P.n_mat : kMatLds;
+  for (int q = threadIdx.x; q < nm; q += blockDim.x) sm[q] = mat_from<R>(v.mat[q]);
+  __syncthreads();
+}
+template <typename R>
+__device__ __forceinline__ MatL<R> mat_of(const MatL<R>* sm, const View<R>& v, uint32_t ph) {
+  if (ph < (uint32_t)kMatLds) return sm[ph];
+  return mat_from<R>(v.mat[ph]);
+}
+
 // wall / rigid extrapolation (local force balance of Adami et al. 2012):
 // p_w = [sum p_f W + sum rho_f (b_f - a_w).(x_w - x_f) W] / sum W,
 // u~_w = 2 u_w - sum u_f W / sum W; returns the number of fluid neighbours
 template <typename R, int DIM, typename It>
-__device__ __forceinline__ uint32_t extrap_one(const View<R>& v, const KC<R>& k, uint32_t i, bool act, It&& it) {
+__device__ __forceinline__ uint32_t extrap_one(const View<R>& v, const KC<R>& k, const MatL<R>* sm, uint32_t i,
+                                               bool act, It&& it) {
   const uint32_t inf = v.info[i];
   const uint32_t kind = ikind(inf);
   R aw[3] = {R(0), R(0), R(0)};
@@ -246,15 +274,15 @@ __device__ __forceinline__ uint32_t extrap_one(const View<R>& v, const KC<R>& k,
     const uint32_t ij = r_to_info(nb.rm.z);
     if (ikind(ij) != KF) return;
     ++c;
-    const MatT<R>& Mj = v.mat[iphase(ij)];
+    const MatL<R> Mj = mat_of<R>(sm, v, iphase(ij));
     const R W = kern_w<R>(ksqrt(r2), k);
     R dot;
     if constexpr (IsExact<R>::v) {
-      dot = (Mj.b[0] - aw[0]) * d0 + (Mj.b[1] - aw[1]) * d1;
-      if (DIM == 3) dot = dot + (Mj.b[2] - aw[2]) * d2;
+      dot = (Mj.b0 - aw[0]) * d0 + (Mj.b1 - aw[1]) * d1;
+      if (DIM == 3) dot = dot + (Mj.b2 - aw[2]) * d2;
     } else {
-      dot = kfma(Mj.b[1] - aw[1], d1, (Mj.b[0] - aw[0]) * d0);
-      if (DIM == 3) dot = kfma(Mj.b[2] - aw[2], d2, dot);
+      dot = kfma(Mj.b1 - aw[1], d1, (Mj.b0 - aw[0]) * d0);
+      if (DIM == 3) dot = kfma(Mj.b2 - aw[2], d2, dot);
     }
     sW = sW + W;
     if constexpr (IsExact<R>::v) {
@@ -345,23 +373,32 @@ __device__ __forceinline__ void pair_force(R rho_a, R p_a, R m_a, R eta_a, R uax
 }
 
 // conduction term of eq. nummeth_thermo_heat_equation for one neighbour
+// (fluid neighbours: V = m/rho; rigid: m/rho0 of the phase; walls only
+// with a prescribed temperature, V = dx^d)
 template <typename R>
-__device__ __forceinline__ void heat_pair(const KC<R>& k, uint32_t kj, const MatT<R>& Mj, const Nbr<R>& nb, R ka,
+__device__ __forceinline__ void heat_pair(const KC<R>& k, uint32_t kj, const MatL<R>& Mj, const Nbr<R>& nb, R ka,
                                           R Ti, R r, R dW, R& hs) {
-  R Vb;
-  if (kj == KF) Vb = kdiv(nb.rm.y, nb.rm.x);
-  else if (kj == KR) Vb = kdiv(nb.rm.y, Mj.rho0);
-  else if (Mj.dirichlet) Vb = k.vol0;
-  else return;
+  const bool wall = kj == KW;
+  const R Vm = kdiv(nb.rm.y, kj == KF ? nb.rm.x : Mj.rho0);
+  const R Vb = wall ? k.vol0 : Vm;
   const R kb = Mj.kappa;
-  if (!(ka + kb > R(0))) return;
+  const bool on = (!wall || Mj.dir != R(0)) && (ka + kb > R(0));
   if constexpr (IsExact<R>::v) {
     const R kk = (R(4) * ka * kb) / (ka + kb);
-    hs = hs + (Vb * kk) * ((Ti - nb.rm.w) / r) * dW;
+    const R add = (Vb * kk) * ((Ti - nb.rm.w) / r) * dW;
+    if (on) hs = hs + add;
   } else {
     const R kk = (R(4) * ka * kb) * __builtin_amdgcn_rcpf(ka + kb);
-    hs = kfma((Vb * kk) * ((Ti - nb.rm.w) * __builtin_amdgcn_rcpf(r)), dW, hs);
+    const R nh = kfma((Vb * kk) * ((Ti - nb.rm.w) * __builtin_amdgcn_rcpf(r)), dW, hs);
+    hs = on ? nh : hs;
   }
+}
+
+// inverse equation of state of a phase: rho = rho0 (p / p0 + 1)
+template <typename R>
+__device__ __forceinline__ R inv_eos(const MatL<R>& M, R p) {
+  if constexpr (IsExact<R>::v) return M.rho0 * (p / M.p0 + R(1));
+  else return M.rho0 * kfma(p, M.inv_p0, R(1));
 }
 
 // Momentum (eq. nummeth_fluid_momentum) of fluid particles with the second
@@ -371,14 +408,15 @@ __device__ __forceinline__ void heat_pair(const KC<R>& k, uint32_t kj, const Mat
 // over the target's neighbours.  Every lane of the wave calls it (the
 // iterator synchronises); only lanes with act set have a target.
 template <typename R, int DIM, int THERMAL, typename It>
-__device__ __forceinline__ void forces_one(const View<R>& v, const Params& P, const KC<R>& k, uint32_t i, bool act,
-                                           int kick, int heat, double t, It&& it) {
+__device__ __forceinline__ void forces_one(const View<R>& v, const Params& P, const KC<R>& k, const MatL<R>* sm,
+                                           uint32_t i, bool act, int kick, int heat, double t, It&& it) {
   const uint32_t inf = v.info[i];
   const uint32_t kind = ikind(inf);
   const bool fluid = kind == KF;
   const V4<R> ui = v.u[i];
   const R Ti = THERMAL ? v.T[i] : R(0);
   const MatT<R>& Mi = v.mat[iphase(inf)];
+  const MatL<R> Li = mat_of<R>(sm, v, iphase(inf));
   const R m_i = v.m[i];
   const R rho_i = v.rho[i];
   const R p_i = v.p[i];
@@ -393,36 +431,32 @@ __device__ __forceinline__ void forces_one(const View<R>& v, const Params& P, co
     if (r2 == R(0)) { coincident = true; return; }
     const uint32_t ij = r_to_info(nb.rm.z);
     const uint32_t kj = ikind(ij);
-    const MatT<R>& Mj = v.mat[iphase(ij)];
+    const bool fj = kj == KF;
+    const MatL<R> Mj = mat_of<R>(sm, v, iphase(ij));
     const R r = ksqrt(r2);
     const R dW = kern_dw<R>(r, k);
-    if (fluid) {
+    if (fluid || fj) {
+      // one pair formula for both couplings: a fluid target against any
+      // neighbour (a wall or rigid neighbour enters with p_w, u~_w, the
+      // density of p_w under the target's phase, the target's mass and
+      // viscosity), and a rigid target against a fluid neighbour (the
+      // rigid side enters the same way under the neighbour's phase);
+      // F(a, b, x_a - x_b) = -F(b, a, x_b - x_a) exactly, so the rigid
+      // target's sum equals that of f_ri = -m_i a_ir
+      const R rB = fj ? nb.rm.x : inv_eos<R>(Li, nb.vp.w);
+      const R rA = fluid ? rho_i : inv_eos<R>(Mj, pw_r);
+      const R pA = fluid ? p_i : pw_r;
+      const R mA = fluid ? m_i : nb.rm.y;
+      const R eA = fluid ? eta_i : Mj.eta;
+      const R mB = fj ? nb.rm.y : m_i;
+      const R eB = fj ? Mj.eta : eta_i;
+      const R uA0 = fluid ? ui.x : vpr.x, uA1 = fluid ? ui.y : vpr.y, uA2 = fluid ? ui.z : vpr.z;
       R F[3];
-      if (kj == KF) {
-        pair_force<R, DIM>(rho_i, p_i, m_i, eta_i, ui.x, ui.y, ui.z, nb.rm.x, nb.vp.w, nb.rm.y, Mj.eta, nb.vp.x,
-                           nb.vp.y, nb.vp.z, d0, d1, d2, r, dW, F);
-      } else {
-        const R p_j = nb.vp.w;
-        R rho_j;
-        if constexpr (IsExact<R>::v) rho_j = Mi.rho0 * (p_j / Mi.p0 + R(1));
-        else rho_j = Mi.rho0 * kfma(p_j, Mi.inv_p0, R(1));
-        pair_force<R, DIM>(rho_i, p_i, m_i, eta_i, ui.x, ui.y, ui.z, rho_j, p_j, m_i, eta_i, nb.vp.x, nb.vp.y,
-                           nb.vp.z, d0, d1, d2, r, dW, F);
-      }
+      pair_force<R, DIM>(rA, pA, mA, eA, uA0, uA1, uA2, rB, nb.vp.w, mB, eB, nb.vp.x, nb.vp.y, nb.vp.z, d0, d1, d2,
+                         r, dW, F);
       acc0 = acc0 + F[0];
       acc1 = acc1 + F[1];
       if (DIM == 3) acc2 = acc2 + F[2];
-    } else if (kj == KF) {
-      const R rho_a = nb.rm.x, p_a = nb.vp.w, m_a = nb.rm.y, eta_a = Mj.eta;
-      R rho_b;
-      if constexpr (IsExact<R>::v) rho_b = Mj.rho0 * (pw_r / Mj.p0 + R(1));
-      else rho_b = Mj.rho0 * kfma(pw_r, Mj.inv_p0, R(1));
-      R F[3];
-      pair_force<R, DIM>(rho_a, p_a, m_a, eta_a, nb.vp.x, nb.vp.y, nb.vp.z, rho_b, pw_r, m_a, eta_a, vpr.x, vpr.y,
-                         vpr.z, -d0, -d1, -d2, r, dW, F);
-      acc0 = acc0 - F[0];
-      acc1 = acc1 - F[1];
-      if (DIM == 3) acc2 = acc2 - F[2];
     } else if (P.contact && r2 < k.dx2 && (kj == KW || ibody(ij) != body_i)) {
       const V4<R> uj = v.u[nb.j];
       R e0, e1, e2 = R(0), en;
@@ -806,10 +840,12 @@ __global__ void __launch_bounds__(64) k_extrapolate_list(View<R> v, Params P, KC
   const uint32_t kind = ikind(v.info[i]);
   const bool need = active && kind != KF;
   if (!__any(need)) return;
+  __shared__ MatL<R> smat[kMatLds];
+  stage_mats<R>(smat, v, P);
   const WaveGeo g = wave_geo<R>(v, P, wi);
   const V4<R> T = to_frame<R>(v.pos[i], k, g.cx_first, 0, 0);
   unsigned long long cr = 0, cw = 0;
-  const uint32_t c = extrap_one<R, DIM>(v, k, i, need, [&](bool ws, auto&& f) {
+  const uint32_t c = extrap_one<R, DIM>(v, k, smat, i, need, [&](bool ws, auto&& f) {
     for_rows<R, DIM>(v, P, k, g, sp, svp, srm, need, w, i, T, ws, f);
   });
   if (need && kind == KR) cr = c;
@@ -836,8 +872,10 @@ __global__ void __launch_bounds__(64) k_forces_list(View<R> v, Params P, KC<R> k
   }
   const bool need = active && kind != KW;
   if (!__any(need)) return;
+  __shared__ MatL<R> smat[kMatLds];
+  stage_mats<R>(smat, v, P);
   const V4<R> T = to_frame<R>(v.pos[i], k, g.cx_first, 0, 0);
-  forces_one<R, DIM, THERMAL>(v, P, k, i, need, kick, heat, t, [&](bool ws, auto&& f) {
+  forces_one<R, DIM, THERMAL>(v, P, k, smat, i, need, kick, heat, t, [&](bool ws, auto&& f) {
     for_rows<R, DIM>(v, P, k, g, sp, svp, srm, need, w, i, T, ws, f);
   });
 }

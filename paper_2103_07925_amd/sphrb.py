@@ -105,6 +105,13 @@ def lib():
     L.sph_scene_read_stats.argtypes = [C.c_void_p, C.POINTER(sph_stats)]
     L.sph_scene_enable_timers.argtypes = [C.c_void_p, C.c_int32]
     L.sph_scene_read_timers.argtypes = [C.c_void_p, _dp, C.POINTER(C.c_int64), _dp, C.c_int64]
+    L.sph_scene_state_bytes.argtypes = [C.c_void_p]
+    L.sph_scene_state_bytes.restype = C.c_size_t
+    L.sph_scene_read_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+    L.sph_state_arena_bytes.argtypes = [C.c_void_p, C.c_size_t, C.POINTER(C.c_int)]
+    L.sph_state_arena_bytes.restype = C.c_size_t
+    L.sph_scene_create_from_state.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p,
+                                              C.POINTER(C.c_void_p)]
     L.sph_scene_destroy.argtypes = [C.c_void_p]
     L.sph_scene_destroy.restype = None
     _lib = L
@@ -208,8 +215,45 @@ def sph_scene_arena_bytes(desc: Desc) -> int:
     return int(nbytes)
 
 
+def sph_state_arena_bytes(blob) -> int:
+    """Device arena bytes a scene re-created from a state image needs."""
+    blob = np.ascontiguousarray(blob, np.uint8)
+    st = C.c_int(0)
+    nbytes = lib().sph_state_arena_bytes(C.c_void_p(blob.ctypes.data), C.c_size_t(blob.nbytes), C.byref(st))
+    _check(st.value, "sph_state_arena_bytes")
+    return int(nbytes)
+
+
 class SphScene:
     """One resident scene: a torch-owned device arena plus the library handle."""
+
+    @classmethod
+    def sph_scene_create_from_state(cls, blob, like, device="cuda", stream=None, arena=None):
+        """Re-create a scene from a state image; `like` is the scene
+        description it was made from (particle count and dimension)."""
+        import torch
+        blob = np.ascontiguousarray(blob, np.uint8)
+        self = cls.__new__(cls)
+        self.sc = like
+        self.n = like.n
+        self.dim = like.dim
+        self.precision = None
+        self._desc = None
+        self.arena_bytes = sph_state_arena_bytes(blob)
+        if arena is None:
+            arena = torch.empty(self.arena_bytes, dtype=torch.uint8, device=device)
+        assert arena.numel() >= self.arena_bytes and arena.data_ptr() % 256 == 0
+        self.arena = arena
+        self.stream = stream if stream is not None else torch.cuda.current_stream(arena.device)
+        h = C.c_void_p()
+        st = lib().sph_scene_create_from_state(C.c_void_p(blob.ctypes.data), C.c_size_t(blob.nbytes),
+                                               C.c_void_p(arena.data_ptr()), C.c_size_t(arena.numel()),
+                                               C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        _check(st, "sph_scene_create_from_state")
+        self.handle = h
+        return self
+
+    from_state = sph_scene_create_from_state
 
     def __init__(self, sc, precision=SPH_FP64, dt=None, device="cuda", stream=None, arena=None):
         import torch
@@ -316,6 +360,16 @@ class SphScene:
         return st
 
     stats = sph_scene_read_stats
+
+    def sph_scene_read_state(self):
+        """State image (header + device arena) as a numpy uint8 array."""
+        nbytes = lib().sph_scene_state_bytes(self.handle)
+        blob = np.empty(nbytes, np.uint8)
+        _check(lib().sph_scene_read_state(self.handle, C.c_void_p(blob.ctypes.data), C.c_size_t(nbytes)),
+               "sph_scene_read_state")
+        return blob
+
+    read_state = sph_scene_read_state
 
     def sph_scene_enable_timers(self, enable=True):
         _check(lib().sph_scene_enable_timers(self.handle, int(enable)), "sph_scene_enable_timers")

@@ -52,3 +52,11 @@ def test_invalid_descriptors_rejected(mutate, what):
         B.sph_scene_arena_bytes(B.Desc(sc, B.SPH_FP64))
     assert e.value.status == B.SPH_E_INVALID
     assert what in B.sph_last_error()
+
+
+@pytest.mark.parametrize("blob", [b"", b"not a state image at all" * 4, b"SPHRBST1" + b"\0" * 64])
+def test_state_images_rejected(blob):
+    """A buffer that is not a whole state image is refused before any device call."""
+    with pytest.raises(B.SphError) as e:
+        B.sph_state_arena_bytes(np.frombuffer(blob, np.uint8) if blob else np.zeros(0, np.uint8))
+    assert e.value.status == B.SPH_E_INVALID
