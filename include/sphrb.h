@@ -152,10 +152,29 @@ int sph_scene_create(const sph_scene_desc *d, void *dev_arena, size_t arena_byte
  * velocity-Verlet scheme" plus the phase switch).  Asynchronous. */
 int sph_scene_step(sph_scene *s, int64_t nsteps);
 
-/* Advance several resident scenes by nsteps each, enqueuing their steps
- * interleaved on their own streams.  Each scene's result is independent of
- * the others. */
-int sph_batch_step(sph_scene *const *scenes, int32_t n, int64_t nsteps);
+/* Batches: several resident scenes advanced together.  Per step, every
+ * scene's per-particle and per-body stages are enqueued on the batch stream
+ * and the three interaction sweeps (density, extrapolation, forces) run as
+ * one launch each over the concatenated waves of all scenes of the same
+ * precision, dimension and thermal flag (a table of per-scene slots in the
+ * caller's device workspace).  Every scene runs exactly the arithmetic of
+ * sph_scene_step, so its results are bit for bit those it gets alone.
+ *   sph_batch_bytes: device workspace for a batch of n scenes (256-byte
+ *     aligned, caller-owned, must outlive the batch).
+ *   sph_batch_create: n >= 1 distinct scenes (SPH_E_INVALID otherwise);
+ *     hip_stream is the batch stream.  The scenes stay owned by the caller
+ *     and must outlive the batch; a scene may be in several batches but
+ *     only one may step it at a time.
+ *   sph_batch_step: enqueues nsteps steps of every scene; asynchronous.
+ *     Work already enqueued on a scene's own stream is waited for, and the
+ *     scene's stream waits for the batch's work, through events.
+ *   sph_batch_destroy: waits for the batch stream and frees the host side. */
+typedef struct sph_batch sph_batch;
+size_t sph_batch_bytes(int32_t n);
+int sph_batch_create(sph_scene *const *scenes, int32_t n, void *dev_ws, size_t ws_bytes, void *hip_stream,
+                     sph_batch **out);
+int sph_batch_step(sph_batch *b, int64_t nsteps);
+void sph_batch_destroy(sph_batch *b);
 
 /* Wait for the scene's stream; returns SPH_E_STATE if a device error is set. */
 int sph_scene_sync(sph_scene *s);

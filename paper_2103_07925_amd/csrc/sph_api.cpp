@@ -100,6 +100,7 @@ struct sph_scene {
   Lists nb;
   uint32_t *wcount, *woff, *wbsum;
   uint32_t* dyn;     // device: [0] rigid particles, [1] bodies
+  unsigned long long* dstep;   // device: steps begun
   double* matb;      // device: body force of every material (FP64)
   PhaseBufs ps;
   double* gpart;
@@ -108,6 +109,28 @@ struct sph_scene {
   int timers;
   std::vector<hipEvent_t>* ev;
   int64_t rec;
+};
+
+// A batch: scenes grouped by (precision, dim, thermal); each group's sweeps
+// run as one launch over a table of slots in the caller's workspace.  The
+// slot table of a step depends on the scenes' buffer parities, which repeat
+// every two steps, so two tables per group are kept and re-uploaded only
+// when a scene was stepped outside the batch.
+struct sph_batch {
+  struct Group {
+    int precision, dim, thermal;
+    std::vector<int> members;
+    uint32_t blocks;
+    size_t off[2];                   // table offsets in the workspace
+    std::vector<char> host[2];       // table images (kept for the async upload)
+    std::vector<int> key[2];         // buffer parities the tables were made for
+  };
+  std::vector<sph_scene*> scenes;
+  std::vector<Group> groups;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  std::vector<hipEvent_t> ev;        // one per scene, plus one for the batch stream
 };
 
 namespace {
@@ -266,6 +289,7 @@ void carve(Carver& cv, sph_scene* s, const Params& P, int64_t nmat) {
   s->gpart = cv.take<double>(5 * kGlobalBlocks);
   s->gout = cv.take<double>(8);
   s->dyn = cv.take<uint32_t>(4);
+  s->dstep = cv.take<unsigned long long>(1);
   s->matb = cv.take<double>(3 * (size_t)nmat);
   // phase switch work space (only with switching enabled)
   const size_t np = P.pswitch ? n : 0, nbp = P.pswitch ? (size_t)std::max(P.maxb, 1) : 0;
@@ -431,6 +455,7 @@ View<R> make_view(sph_scene* s, int ip, int iu, int iT) {
   v.pairs = s->pairs;
   v.nb = s->nb;
   v.dyn = s->dyn;
+  v.dstep = s->dstep;
   v.ps = s->ps;
   return v;
 }
@@ -461,32 +486,18 @@ void sort_and_permute(sph_scene* s) {
   s->iT = 1 - s->iT;
 }
 
-// densities, extrapolation, forces (+ heat), body sums
+// The step's stages.  pre_step: counters, first kick and drift, bodies,
+// rigid and wall poses, sort; sweeps: density, extrapolation, forces (+ heat,
+// second fluid kick); post_step: body sums and second body kick, rigid
+// velocities, phase switch.  A batch runs the sweeps of all its scenes as
+// one launch per sweep between the scenes' pre and post stages.
 template <typename R>
-void evaluate(sph_scene* s, int kick, int heat, double t, hipEvent_t* ev) {
-  const KC<R> k = make_kc<R>(s->P);
-  View<R> v = cur<R>(s);
-  Launch<R>::density(v, s->P, k, s->stream);
-  if (ev) (void)hipEventRecord(ev[3], s->stream);
-  Launch<R>::extrapolate(v, s->P, k, s->stream);
-  if (ev) (void)hipEventRecord(ev[4], s->stream);
-  Launch<R>::forces(v, s->P, k, kick, heat, t, s->stream);
-  if (ev) (void)hipEventRecord(ev[5], s->stream);
-  s->iu = 1 - s->iu;
-  if (s->P.thermal) s->iT = 1 - s->iT;
-  launch_body_reduce(s->bodies, s->s_f, s->s_rk, s->P, kick, s->P.pswitch ? s->dyn + 1 : nullptr, s->stream);
-  if (ev) (void)hipEventRecord(ev[6], s->stream);
-}
-
-template <typename R>
-void one_step(sph_scene* s) {
+void pre_step(sph_scene* s, hipEvent_t* ev) {
   const Params& P = s->P;
   const KC<R> k = make_kc<R>(P);
   const double t_new = (double)(s->step + 1) * P.dt;
-  hipEvent_t* ev = nullptr;
-  if (s->timers && s->rec < SPH_TIMER_STEPS) ev = &(*s->ev)[(size_t)s->rec * (SPH_TIMER_STAGES + 1)];
-  zero_pairs(s, false);
   if (ev) (void)hipEventRecord(ev[0], s->stream);
+  launch_step_begin(s->pairs, s->dstep, s->stream);
   View<R> v = cur<R>(s);
   Launch<R>::kick_drift(v, P, k, s->sb, s->stream);
   launch_body_kick_drift(s->bodies, P, P.pswitch ? s->dyn + 1 : nullptr, s->stream);
@@ -495,15 +506,105 @@ void one_step(sph_scene* s) {
   if (ev) (void)hipEventRecord(ev[1], s->stream);
   sort_and_permute<R>(s);
   if (ev) (void)hipEventRecord(ev[2], s->stream);
-  evaluate<R>(s, 1, 1, t_new, ev);
-  v = cur<R>(s);
+}
+
+template <typename R>
+void sweeps(sph_scene* s, int kick, int heat, hipEvent_t* ev) {
+  const KC<R> k = make_kc<R>(s->P);
+  View<R> v = cur<R>(s);
+  Launch<R>::density(v, s->P, k, s->stream);
+  if (ev) (void)hipEventRecord(ev[3], s->stream);
+  Launch<R>::extrapolate(v, s->P, k, s->stream);
+  if (ev) (void)hipEventRecord(ev[4], s->stream);
+  Launch<R>::forces(v, s->P, k, kick, heat, s->stream);
+  if (ev) (void)hipEventRecord(ev[5], s->stream);
+}
+
+// the sweeps wrote u (and T) into the other buffer; body sums
+template <typename R>
+void after_sweeps(sph_scene* s, int kick, hipEvent_t* ev) {
+  s->iu = 1 - s->iu;
+  if (s->P.thermal) s->iT = 1 - s->iT;
+  launch_body_reduce(s->bodies, s->s_f, s->s_rk, s->P, kick, s->P.pswitch ? s->dyn + 1 : nullptr, s->stream);
+  if (ev) (void)hipEventRecord(ev[6], s->stream);
+}
+
+template <typename R>
+void post_step(sph_scene* s, hipEvent_t* ev) {
+  const Params& P = s->P;
+  after_sweeps<R>(s, 1, ev);
+  View<R> v = cur<R>(s);
   Launch<R>::rigid_velocity(v, P, s->stream);
-  if (P.pswitch) Launch<R>::phase_switch(v, P, k, s->matb, s->stream);
+  if (P.pswitch) Launch<R>::phase_switch(v, P, make_kc<R>(P), s->matb, s->stream);
   if (ev) {
     (void)hipEventRecord(ev[7], s->stream);
     s->rec += 1;
   }
   s->step += 1;
+}
+
+size_t slot_bytes(int precision) { return precision == SPH_FP64 ? sizeof(Slot<double>) : sizeof(Slot<float>); }
+constexpr size_t kSlotMax = sizeof(Slot<double>) > sizeof(Slot<float>) ? sizeof(Slot<double>) : sizeof(Slot<float>);
+
+template <typename R>
+void fill_slot(sph_scene* s, uint32_t b0, uint32_t nb, char* dst) {
+  Slot<R> sl;
+  std::memset(&sl, 0, sizeof(sl));
+  sl.v = cur<R>(s);
+  sl.P = s->P;
+  sl.k = make_kc<R>(s->P);
+  sl.b0 = b0;
+  sl.nb = nb;
+  std::memcpy(dst, &sl, sizeof(sl));
+}
+
+// the group's slot table for the scenes' current buffer parities: one of the
+// two kept tables, or a new one written over the table not used last
+int group_table(sph_batch* b, sph_batch::Group& g, int* which_out) {
+  std::vector<int> key;
+  for (int m : g.members) {
+    sph_scene* s = b->scenes[m];
+    key.push_back(s->ip * 4 + s->iu * 2 + s->iT);
+  }
+  for (int w = 0; w < 2; ++w)
+    if (key == g.key[w]) {
+      *which_out = w;
+      return SPH_OK;
+    }
+  const int which = g.key[0].empty() ? 0 : 1;
+  *which_out = which;
+  // a table in flight is replaced: wait for the batch stream first
+  if (!g.key[which].empty()) HIP_TRY(hipStreamSynchronize(b->stream));
+  const size_t sb = slot_bytes(g.precision);
+  g.host[which].assign(g.members.size() * sb, 0);
+  uint32_t b0 = 0;
+  for (size_t q = 0; q < g.members.size(); ++q) {
+    sph_scene* s = b->scenes[g.members[q]];
+    const uint32_t nb = (uint32_t)((s->P.max_waves + 7) / 8 * 8);
+    if (g.precision == SPH_FP64) fill_slot<double>(s, b0, nb, &g.host[which][q * sb]);
+    else fill_slot<float>(s, b0, nb, &g.host[which][q * sb]);
+    b0 += nb;
+  }
+  g.blocks = b0;
+  HIP_TRY(hipMemcpyAsync(b->ws + g.off[which], g.host[which].data(), g.host[which].size(), hipMemcpyHostToDevice,
+                         b->stream));
+  g.key[which] = key;
+  return SPH_OK;
+}
+
+template <typename R>
+void group_sweep(sph_batch* b, sph_batch::Group& g, int which, int stage) {
+  Launch<R>::batch_sweep(stage, reinterpret_cast<const Slot<R>*>(b->ws + g.off[which]), (int)g.members.size(),
+                         g.dim, g.thermal, g.blocks, 1, 1, b->stream);
+}
+
+template <typename R>
+void one_step(sph_scene* s) {
+  hipEvent_t* ev = nullptr;
+  if (s->timers && s->rec < SPH_TIMER_STEPS) ev = &(*s->ev)[(size_t)s->rec * (SPH_TIMER_STAGES + 1)];
+  pre_step<R>(s, ev);
+  sweeps<R>(s, 1, 1, ev);
+  post_step<R>(s, ev);
 }
 
 template <typename R>
@@ -680,6 +781,7 @@ int create_impl(const sph_scene_desc* d, sph_scene* s) {
   launch_fill_u32(s->ps.ctr, 0u, 8, st);
   if (P.pswitch) launch_fill_u32(s->ps.dirty, 0u, std::max(P.maxb, 1), st);
   zero_pairs(s, true);
+  launch_fill_u32(reinterpret_cast<uint32_t*>(s->dstep), 0u, 2, st);
   s->ip = 0;
   s->iu = 0;
   s->iT = 0;
@@ -691,7 +793,8 @@ int create_impl(const sph_scene_desc* d, sph_scene* s) {
   }
   // first sort, then one evaluation without time update
   sort_and_permute<R>(s);
-  evaluate<R>(s, 0, 0, 0.0, nullptr);
+  sweeps<R>(s, 0, 0, nullptr);
+  after_sweeps<R>(s, 0, nullptr);
   HIP_TRY(hipStreamSynchronize(st));
   uint32_t err = 0;
   HIP_TRY(hipMemcpy(&err, s->err, 4, hipMemcpyDeviceToHost));
@@ -977,18 +1080,118 @@ int sph_scene_step(sph_scene* s, int64_t nsteps) {
   return SPH_OK;
 }
 
-int sph_batch_step(sph_scene* const* scenes, int32_t n, int64_t nsteps) {
-  if (!scenes || n < 0 || nsteps < 0) return fail(SPH_E_INVALID, "bad batch");
-  for (int64_t k = 0; k < nsteps; ++k)
-    for (int32_t q = 0; q < n; ++q) {
-      sph_scene* s = scenes[q];
-      if (!s) return fail(SPH_E_INVALID, "null scene in batch");
-      if (s->precision == SPH_FP64) one_step<double>(s);
-      else one_step<float>(s);
+size_t sph_batch_bytes(int32_t n) {
+  if (n <= 0) return 0;
+  // two tables per group, at most 8 groups (precision x dim x thermal)
+  return 2 * ((size_t)n * kSlotMax + 8 * 256) + 256;
+}
+
+int sph_batch_create(sph_scene* const* scenes, int32_t n, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                     sph_batch** out) {
+  if (!out) return fail(SPH_E_INVALID, "null out");
+  *out = nullptr;
+  if (!scenes || n <= 0) return fail(SPH_E_INVALID, "a batch needs at least one scene");
+  for (int32_t q = 0; q < n; ++q) {
+    if (!scenes[q]) return fail(SPH_E_INVALID, "null scene in batch");
+    for (int32_t r = 0; r < q; ++r)
+      if (scenes[r] == scenes[q]) return fail(SPH_E_INVALID, "scene listed twice in batch");
+  }
+  if (!dev_ws || ws_bytes < sph_batch_bytes(n)) return fail(SPH_E_NOMEM, "batch workspace too small");
+  if ((reinterpret_cast<uintptr_t>(dev_ws) & 255u) != 0) return fail(SPH_E_INVALID, "workspace must be 256-byte aligned");
+  sph_batch* b = new (std::nothrow) sph_batch;
+  if (!b) return fail(SPH_E_NOMEM, "host allocation");
+  b->scenes.assign(scenes, scenes + n);
+  b->stream = (hipStream_t)hip_stream;
+  b->ws = (char*)dev_ws;
+  b->ws_bytes = ws_bytes;
+  size_t off = 0;
+  for (int32_t q = 0; q < n; ++q) {
+    sph_scene* s = scenes[q];
+    sph_batch::Group* g = nullptr;
+    for (auto& gg : b->groups)
+      if (gg.precision == s->precision && gg.dim == s->P.dim && gg.thermal == s->P.thermal) g = &gg;
+    if (!g) {
+      b->groups.emplace_back();
+      g = &b->groups.back();
+      g->precision = s->precision;
+      g->dim = s->P.dim;
+      g->thermal = s->P.thermal;
+      g->blocks = 0;
     }
+    g->members.push_back(q);
+  }
+  for (auto& g : b->groups)
+    for (int w = 0; w < 2; ++w) {
+      g.off[w] = off;
+      off = align_up(off + g.members.size() * slot_bytes(g.precision));
+    }
+  b->ev.assign((size_t)n + 1, nullptr);
+  for (auto& e : b->ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      for (auto& e2 : b->ev)
+        if (e2) (void)hipEventDestroy(e2);
+      delete b;
+      return fail(SPH_E_DEVICE, "hipEventCreate");
+    }
+  *out = b;
+  return SPH_OK;
+}
+
+int sph_batch_step(sph_batch* b, int64_t nsteps) {
+  if (!b) return fail(SPH_E_INVALID, "null batch");
+  if (nsteps < 0) return fail(SPH_E_INVALID, "negative step count");
+  if (nsteps == 0) return SPH_OK;
+  const size_t n = b->scenes.size();
+  std::vector<hipStream_t> own(n);
+  bool other = false;
+  for (size_t q = 0; q < n; ++q) {
+    sph_scene* s = b->scenes[q];
+    own[q] = s->stream;
+    if (s->stream != b->stream) {
+      HIP_TRY(hipEventRecord(b->ev[q], s->stream));
+      HIP_TRY(hipStreamWaitEvent(b->stream, b->ev[q], 0));
+      other = true;
+    }
+    s->stream = b->stream;
+  }
+  int st = SPH_OK;
+  for (int64_t k = 0; k < nsteps && st == SPH_OK; ++k) {
+    for (sph_scene* s : b->scenes) {
+      if (s->precision == SPH_FP64) pre_step<double>(s, nullptr);
+      else pre_step<float>(s, nullptr);
+    }
+    std::vector<int> which(b->groups.size());
+    for (size_t g = 0; g < b->groups.size() && st == SPH_OK; ++g) st = group_table(b, b->groups[g], &which[g]);
+    if (st != SPH_OK) break;
+    for (int stage = 0; stage < 3; ++stage)
+      for (size_t g = 0; g < b->groups.size(); ++g) {
+        sph_batch::Group& G = b->groups[g];
+        if (G.precision == SPH_FP64) group_sweep<double>(b, G, which[g], stage);
+        else group_sweep<float>(b, G, which[g], stage);
+      }
+    for (sph_scene* s : b->scenes) {
+      if (s->precision == SPH_FP64) post_step<double>(s, nullptr);
+      else post_step<float>(s, nullptr);
+    }
+  }
+  for (size_t q = 0; q < n; ++q) b->scenes[q]->stream = own[q];
+  if (other) {
+    HIP_TRY(hipEventRecord(b->ev[n], b->stream));
+    for (size_t q = 0; q < n; ++q)
+      if (own[q] != b->stream) HIP_TRY(hipStreamWaitEvent(own[q], b->ev[n], 0));
+  }
+  if (st != SPH_OK) return st;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(SPH_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
   return SPH_OK;
+}
+
+void sph_batch_destroy(sph_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  for (auto& e : b->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete b;
 }
 
 int sph_scene_sync(sph_scene* s) {

@@ -167,7 +167,17 @@ struct View {
   unsigned long long* pairs;   // [0] last evaluation, [1] running total, [2..4] by target kind
   Lists nb;
   uint32_t* dyn;               // [0] rigid particles, [1] bodies (change with phase switches)
+  unsigned long long* dstep;   // steps begun (the step being taken, from 1)
   PhaseBufs ps;
+};
+
+// one scene of a batched sweep
+template <typename R>
+struct Slot {
+  View<R> v;
+  Params P;
+  KC<R> k;
+  uint32_t b0, nb;   // first block in the batched grid and block count (multiples of 8)
 };
 
 struct SortBufs {
@@ -190,7 +200,10 @@ struct Launch {
   static void gather(const View<R>& src, const View<R>& dst, const Params& P, SortBufs sb, hipStream_t st);
   static void density(const View<R>& v, const Params& P, const KC<R>& k, hipStream_t st);
   static void extrapolate(const View<R>& v, const Params& P, const KC<R>& k, hipStream_t st);
-  static void forces(const View<R>& v, const Params& P, const KC<R>& k, int kick, int heat, double t, hipStream_t st);
+  static void forces(const View<R>& v, const Params& P, const KC<R>& k, int kick, int heat, hipStream_t st);
+  // stage 0 density, 1 extrapolation, 2 forces, over all slots of the table
+  static void batch_sweep(int stage, const Slot<R>* tab, int ns, int dim, int thermal, uint32_t blocks, int kick,
+                          int heat, hipStream_t st);
   static void rigid_velocity(const View<R>& v, const Params& P, hipStream_t st);
   static void global_sums(const View<R>& v, const Params& P, double* partials, int nblocks, double* out, hipStream_t st);
   static void nb_count(const View<R>& v, const Params& P, const KC<R>& k, uint32_t* cnt, hipStream_t st);
@@ -201,6 +214,7 @@ struct Launch {
 
 // precision-independent launchers
 void launch_fill_u32(uint32_t* p, uint32_t val, int64_t n, hipStream_t st);
+void launch_step_begin(unsigned long long* pairs, unsigned long long* dstep, hipStream_t st);
 // gate (may be NULL): the scan is skipped when gate[0] == 0
 void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum, hipStream_t st,
                      const uint32_t* gate = nullptr);

@@ -705,11 +705,10 @@ __device__ __forceinline__ int wave_max_i(int x) {
 template <int DIM> struct RowCap { static constexpr int v = DIM == 3 ? 64 : 32; };
 
 template <typename R, int DIM>
-__global__ void __launch_bounds__(64) k_build_density(View<R> v, Params P, KC<R> k) {
+__device__ __forceinline__ void build_density_wave(const View<R>& v, const Params& P, const KC<R>& k, int w) {
   constexpr int CAP = Nb<DIM>::cap, NR = Nb<DIM>::rows, WIN = Win<R>::v, RC = RowCap<DIM>::v;
   __shared__ V4<R> stg[WIN];
   __shared__ uint16_t rl[RC * 64];
-  const int w = xcd_wave(blockIdx.x, gridDim.x);
   if (w >= (int)*v.nb.nwaves) return;
   const WaveInfo wi = v.nb.table[w];
   const int lane = threadIdx.x;
@@ -828,10 +827,14 @@ __global__ void __launch_bounds__(64) k_build_density(View<R> v, Params P, KC<R>
 }
 
 template <typename R, int DIM>
-__global__ void __launch_bounds__(64) k_extrapolate_list(View<R> v, Params P, KC<R> k) {
+__global__ void __launch_bounds__(64) k_build_density(View<R> v, Params P, KC<R> k) {
+  build_density_wave<R, DIM>(v, P, k, xcd_wave(blockIdx.x, gridDim.x));
+}
+
+template <typename R, int DIM>
+__device__ __forceinline__ void extrapolate_wave(const View<R>& v, const Params& P, const KC<R>& k, int w) {
   constexpr int CAP = Nb<DIM>::cap, WIN = Win<R>::v;
   __shared__ V4<R> sp[WIN], svp[WIN], srm[WIN];
-  const int w = xcd_wave(blockIdx.x, gridDim.x);
   if (w >= (int)*v.nb.nwaves) return;
   const WaveInfo wi = v.nb.table[w];
   const int lane = threadIdx.x;
@@ -854,11 +857,17 @@ __global__ void __launch_bounds__(64) k_extrapolate_list(View<R> v, Params P, KC
   block_add_pairs(v.pairs, cw, 4);
 }
 
+template <typename R, int DIM>
+__global__ void __launch_bounds__(64) k_extrapolate_list(View<R> v, Params P, KC<R> k) {
+  extrapolate_wave<R, DIM>(v, P, k, xcd_wave(blockIdx.x, gridDim.x));
+}
+
+// t = (steps begun) x dt, from the scene's device step counter
 template <typename R, int DIM, int THERMAL>
-__global__ void __launch_bounds__(64) k_forces_list(View<R> v, Params P, KC<R> k, int kick, int heat, double t) {
+__device__ __forceinline__ void forces_wave(const View<R>& v, const Params& P, const KC<R>& k, int w, int kick,
+                                            int heat) {
   constexpr int CAP = Nb<DIM>::cap, WIN = Win<R>::v;
   __shared__ V4<R> sp[WIN], svp[WIN], srm[WIN];
-  const int w = xcd_wave(blockIdx.x, gridDim.x);
   if (w >= (int)*v.nb.nwaves) return;
   const WaveInfo wi = v.nb.table[w];
   const int lane = threadIdx.x;
@@ -875,9 +884,71 @@ __global__ void __launch_bounds__(64) k_forces_list(View<R> v, Params P, KC<R> k
   __shared__ MatL<R> smat[kMatLds];
   stage_mats<R>(smat, v, P);
   const V4<R> T = to_frame<R>(v.pos[i], k, g.cx_first, 0, 0);
+  const double t = (double)(*v.dstep) * P.dt;
   forces_one<R, DIM, THERMAL>(v, P, k, smat, i, need, kick, heat, t, [&](bool ws, auto&& f) {
     for_rows<R, DIM>(v, P, k, g, sp, svp, srm, need, w, i, T, ws, f);
   });
+}
+
+template <typename R, int DIM, int THERMAL>
+__global__ void __launch_bounds__(64) k_forces_list(View<R> v, Params P, KC<R> k, int kick, int heat) {
+  forces_wave<R, DIM, THERMAL>(v, P, k, xcd_wave(blockIdx.x, gridDim.x), kick, heat);
+}
+
+// ---------------------------------------------------------------------------
+// batched sweeps: one launch over the concatenated waves of several scenes
+// of the same kind.  Scene s owns blocks [b0, b0 + nb) of the grid (b0 and
+// nb multiples of 8, so a scene's blocks keep their XCD assignment) and runs
+// exactly the code of the single-scene kernels.
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__device__ __forceinline__ int find_slot(const Slot<R>* tab, int ns, uint32_t b) {
+  int lo = 0, hi = ns;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (tab[mid].b0 <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <typename R, int DIM>
+__global__ void __launch_bounds__(64) k_build_density_batch(const Slot<R>* tab, int ns) {
+  const Slot<R>& S = tab[find_slot<R>(tab, ns, blockIdx.x)];
+  const View<R> v = S.v;
+  const Params P = S.P;
+  const KC<R> k = S.k;
+  build_density_wave<R, DIM>(v, P, k, xcd_wave((int)(blockIdx.x - S.b0), (int)S.nb));
+}
+
+template <typename R, int DIM>
+__global__ void __launch_bounds__(64) k_extrapolate_batch(const Slot<R>* tab, int ns) {
+  const Slot<R>& S = tab[find_slot<R>(tab, ns, blockIdx.x)];
+  const View<R> v = S.v;
+  const Params P = S.P;
+  const KC<R> k = S.k;
+  extrapolate_wave<R, DIM>(v, P, k, xcd_wave((int)(blockIdx.x - S.b0), (int)S.nb));
+}
+
+template <typename R, int DIM, int THERMAL>
+__global__ void __launch_bounds__(64) k_forces_batch(const Slot<R>* tab, int ns, int kick, int heat) {
+  const Slot<R>& S = tab[find_slot<R>(tab, ns, blockIdx.x)];
+  const View<R> v = S.v;
+  const Params P = S.P;
+  const KC<R> k = S.k;
+  forces_wave<R, DIM, THERMAL>(v, P, k, xcd_wave((int)(blockIdx.x - S.b0), (int)S.nb), kick, heat);
+}
+
+// start of a step: per-evaluation pair counters cleared, step counter advanced
+__global__ void __launch_bounds__(64) k_step_begin(unsigned long long* pairs, unsigned long long* dstep) {
+  if (threadIdx.x == 0) {
+    pairs[0] = 0ull;
+    pairs[2] = 0ull;
+    pairs[3] = 0ull;
+    pairs[4] = 0ull;
+    dstep[0] = dstep[0] + 1ull;
+  }
 }
 
 // neighbour export from the lists (diagnostic): counts, then ids
@@ -1552,6 +1623,10 @@ void launch_fill_u32(uint32_t* p, uint32_t val, int64_t n, hipStream_t st) {
   if (n > 0) k_fill_u32<<<nblk(n), 256, 0, st>>>(p, val, n);
 }
 
+void launch_step_begin(unsigned long long* pairs, unsigned long long* dstep, hipStream_t st) {
+  k_step_begin<<<1, 64, 0, st>>>(pairs, dstep);
+}
+
 void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum, hipStream_t st,
                      const uint32_t* gate) {
   const int64_t nb = (n + 1023) / 1024;
@@ -1636,16 +1711,33 @@ void Launch<R>::extrapolate(const View<R>& v, const Params& P, const KC<R>& k, h
   else k_extrapolate_list<R, 3><<<g, 64, 0, st>>>(v, P, k);
 }
 template <typename R>
-void Launch<R>::forces(const View<R>& v, const Params& P, const KC<R>& k, int kick, int heat, double t,
-                       hipStream_t st) {
+void Launch<R>::forces(const View<R>& v, const Params& P, const KC<R>& k, int kick, int heat, hipStream_t st) {
   if (P.n <= 0) return;
   const unsigned g = (unsigned)P.max_waves;
   if (P.thermal) {
-    if (P.dim == 2) k_forces_list<R, 2, 1><<<g, 64, 0, st>>>(v, P, k, kick, heat, t);
-    else k_forces_list<R, 3, 1><<<g, 64, 0, st>>>(v, P, k, kick, heat, t);
+    if (P.dim == 2) k_forces_list<R, 2, 1><<<g, 64, 0, st>>>(v, P, k, kick, heat);
+    else k_forces_list<R, 3, 1><<<g, 64, 0, st>>>(v, P, k, kick, heat);
   } else {
-    if (P.dim == 2) k_forces_list<R, 2, 0><<<g, 64, 0, st>>>(v, P, k, kick, heat, t);
-    else k_forces_list<R, 3, 0><<<g, 64, 0, st>>>(v, P, k, kick, heat, t);
+    if (P.dim == 2) k_forces_list<R, 2, 0><<<g, 64, 0, st>>>(v, P, k, kick, heat);
+    else k_forces_list<R, 3, 0><<<g, 64, 0, st>>>(v, P, k, kick, heat);
+  }
+}
+template <typename R>
+void Launch<R>::batch_sweep(int stage, const Slot<R>* tab, int ns, int dim, int thermal, uint32_t blocks, int kick,
+                            int heat, hipStream_t st) {
+  if (ns <= 0 || blocks == 0) return;
+  if (stage == 0) {
+    if (dim == 2) k_build_density_batch<R, 2><<<blocks, 64, 0, st>>>(tab, ns);
+    else k_build_density_batch<R, 3><<<blocks, 64, 0, st>>>(tab, ns);
+  } else if (stage == 1) {
+    if (dim == 2) k_extrapolate_batch<R, 2><<<blocks, 64, 0, st>>>(tab, ns);
+    else k_extrapolate_batch<R, 3><<<blocks, 64, 0, st>>>(tab, ns);
+  } else if (thermal) {
+    if (dim == 2) k_forces_batch<R, 2, 1><<<blocks, 64, 0, st>>>(tab, ns, kick, heat);
+    else k_forces_batch<R, 3, 1><<<blocks, 64, 0, st>>>(tab, ns, kick, heat);
+  } else {
+    if (dim == 2) k_forces_batch<R, 2, 0><<<blocks, 64, 0, st>>>(tab, ns, kick, heat);
+    else k_forces_batch<R, 3, 0><<<blocks, 64, 0, st>>>(tab, ns, kick, heat);
   }
 }
 template <typename R>

@@ -94,7 +94,13 @@ def lib():
     L.sph_scene_create.argtypes = [C.POINTER(sph_scene_desc), C.c_void_p, C.c_size_t, C.c_void_p,
                                    C.POINTER(C.c_void_p)]
     L.sph_scene_step.argtypes = [C.c_void_p, C.c_int64]
-    L.sph_batch_step.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.c_int64]
+    L.sph_batch_bytes.argtypes = [C.c_int32]
+    L.sph_batch_bytes.restype = C.c_size_t
+    L.sph_batch_create.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                                   C.POINTER(C.c_void_p)]
+    L.sph_batch_step.argtypes = [C.c_void_p, C.c_int64]
+    L.sph_batch_destroy.argtypes = [C.c_void_p]
+    L.sph_batch_destroy.restype = None
     L.sph_scene_sync.argtypes = [C.c_void_p]
     L.sph_scene_read_particles.argtypes = [C.c_void_p, C.c_uint32, _dp]
     L.sph_scene_read_bodies.argtypes = [C.c_void_p, _dp, C.c_int32, C.POINTER(C.c_int32)]
@@ -391,6 +397,41 @@ class SphScene:
         return out
 
 
-def sph_batch_step(scenes, nsteps=1):
-    arr = (C.c_void_p * max(len(scenes), 1))(*[s.handle.value for s in scenes])
-    _check(lib().sph_batch_step(arr, len(scenes), int(nsteps)), "sph_batch_step")
+class SphBatch:
+    """Scenes advanced together (one launch per interaction sweep over all of
+    them); the device workspace is a torch tensor owned by this object."""
+
+    def __init__(self, scenes, stream=None, device="cuda"):
+        import torch
+        self.scenes = list(scenes)
+        n = len(self.scenes)
+        nbytes = int(lib().sph_batch_bytes(n))
+        self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.ws.device)
+        arr = (C.c_void_p * max(n, 1))(*[s.handle.value for s in self.scenes])
+        h = C.c_void_p()
+        _check(lib().sph_batch_create(arr, n, C.c_void_p(self.ws.data_ptr()), C.c_size_t(self.ws.numel()),
+                                      C.c_void_p(self.stream.cuda_stream), C.byref(h)), "sph_batch_create")
+        self.handle = h
+
+    def sph_batch_step(self, nsteps=1):
+        _check(lib().sph_batch_step(self.handle, int(nsteps)), "sph_batch_step")
+
+    step = sph_batch_step
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            lib().sph_batch_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    sph_batch_destroy = close
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sph_batch_bytes(n):
+    return int(lib().sph_batch_bytes(int(n)))
