@@ -276,11 +276,10 @@ void carve(Carver& cv, sph_scene* s, const Params& P, int64_t nmat) {
   s->err = cv.take<uint32_t>(4);
   s->pairs = cv.take<unsigned long long>(6);
   // compact neighbour lists: one slot per possible wave
-  const int cap = P.dim == 3 ? 320 : 64, nsr = P.dim == 3 ? 9 : 3;
+  const int cap = P.dim == 3 ? 192 : 64, nsr = P.dim == 3 ? 9 : 3;
   s->nb.table = cv.take<WaveInfo>((size_t)P.max_waves);
   s->nb.ent = cv.take<uint16_t>((size_t)P.max_waves * cap * 64);
-  s->nb.rcnt = cv.take<uint8_t>((size_t)P.max_waves * nsr * 64);
-  s->nb.rbase = cv.take<uint16_t>((size_t)P.max_waves * nsr);
+  s->nb.cnt = cv.take<uint8_t>((size_t)P.max_waves * 64);
   s->nb.jlo = cv.take<uint32_t>((size_t)P.max_waves * nsr);
   s->wcount = cv.take<uint32_t>((size_t)P.nrows);
   s->woff = cv.take<uint32_t>((size_t)P.nrows + 1);

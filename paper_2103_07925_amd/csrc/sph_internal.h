@@ -75,16 +75,14 @@ struct WaveInfo {
   uint32_t p0, cnt, row, pad;
 };
 
-// compact neighbour lists, [wave][entry][lane] (16-bit entries); the
-// entries of stencil row rr start at entry rbase[wave][rr] for every lane,
-// rcnt[wave][rr][lane] of them belong to the lane; jlo is the first
-// candidate index of every stencil row
+// compact neighbour lists, [wave][entry][lane], 16-bit entries: stencil row
+// (bits 12-15) and offset from that row's first candidate jlo[wave][row];
+// every lane's entries in the canonical order
 struct Lists {
   WaveInfo* table;
   uint32_t* nwaves;
   uint16_t* ent;
-  uint8_t* rcnt;
-  uint16_t* rbase;
+  uint8_t* cnt;        // entries of every lane (self included), [wave][lane]
   uint32_t* jlo;
 };
 

@@ -544,7 +544,7 @@ __device__ __forceinline__ void forces_one(const View<R>& v, const Params& P, co
 // ---------------------------------------------------------------------------
 
 template <int DIM> struct Nb {
-  static constexpr int cap = DIM == 3 ? 320 : 64;
+  static constexpr int cap = DIM == 3 ? 192 : 64;   // entries per lane (self included)
   static constexpr int rows = DIM == 3 ? 9 : 3;
 };
 template <typename R> struct Win { static constexpr int v = 256; };
@@ -607,58 +607,52 @@ __device__ __forceinline__ R dist2(const V4<R>& T, const V4<R>& s, R& d0, R& d1,
   return r2;
 }
 
-// Walk one lane's list row by row: every stencil row's window is staged in
-// LDS (positions in the wave frame and the vp / rm records), loaded with
-// coalesced reads by the whole wave; each lane then visits its entries of
-// that row from LDS.  Must be reached by all 64 lanes (it synchronises).
-template <typename R, int DIM, typename F>
-__device__ __forceinline__ void for_rows(const View<R>& v, const Params& P, const KC<R>& k, const WaveGeo& g,
-                                         V4<R>* sp, V4<R>* svp, V4<R>* srm, bool active, int w, uint32_t i,
-                                         const V4<R>& T, bool with_self, F&& visit) {
-  constexpr int NR = Nb<DIM>::rows, WIN = Win<R>::v, CAP = Nb<DIM>::cap;
-  const int lane = threadIdx.x;
-  const int nx = P.nc[0], ny = P.nc[1], nz = P.nc[2];
-  const uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + lane;
-  for (int rr = 0; rr < NR; ++rr) {
-    const int dz = DIM == 3 ? rr / 3 - 1 : 0, dy = rr % 3 - 1;
-    const int yy = g.cy + dy, zz = g.cz + dz;
-    if (yy < 0 || yy >= ny || zz < 0 || zz >= nz) continue;
-    const uint32_t rb2 = (uint32_t)((zz * ny + yy) * nx);
-    const uint32_t jlo = v.cstart[rb2 + g.clo], jhi = v.cstart[rb2 + g.chi + 1];
-    const int tb = v.nb.rbase[(size_t)w * NR + rr];
-    const int c = active ? (int)v.nb.rcnt[((size_t)w * NR + rr) * 64 + lane] : 0;
-    int t = 0;
-    uint32_t e = c > 0 ? gl[(size_t)tb * 64] : 0xffffu;
-    for (uint32_t seg = jlo; seg < jhi; seg += (uint32_t)WIN) {
-      const int ns = (int)(jhi - seg < (uint32_t)WIN ? jhi - seg : (uint32_t)WIN);
-      for (int q = lane; q < ns; q += 64) {
-        const uint32_t j = seg + (uint32_t)q;
-        sp[q] = to_frame<R>(v.pos[j], k, g.cx_first, dy, dz);
-        svp[q] = v.vp[j];
-        srm[q] = v.rm[j];
-      }
-      __syncthreads();
-      const uint32_t lo = seg - jlo, hi = lo + (uint32_t)ns;
-      while (t < c) {
-        if ((e & 0xfffu) >= hi) break;
-        const int q = (int)((e & 0xfffu) - lo);
-        const uint32_t en = (t + 1 < c) ? gl[(size_t)(tb + t + 1) * 64] : 0xffffu;
-        const uint32_t j = seg + (uint32_t)q;
-        if (j != i || with_self) {
-          R d0, d1, d2;
-          const R r2 = dist2<R, DIM>(T, sp[q], d0, d1, d2);
-          Nbr<R> nb;
-          nb.j = j;
-          nb.vp = svp[q];
-          nb.rm = srm[q];
-          visit(nb, d0, d1, d2, r2);
-        }
-        e = en;
-        ++t;
-      }
-      __syncthreads();
-    }
+__device__ __forceinline__ int wave_max_i(int x) {
+  for (int off = 32; off > 0; off >>= 1) {
+    int y = __shfl_xor(x, off, 64);
+    x = y > x ? y : x;
   }
+  return x;
+}
+
+// Walk one lane's list: entry q of lane l sits at [wave][q][l], so the
+// wave reads one 128-byte line per step; the entry gives the stencil row
+// (bits 12-15) and the offset from that row's first candidate, whose index
+// jl[] holds (LDS).  The neighbour's position and records are read straight
+// from the sorted arrays (they stay in the L1/L2 caches across the lanes and
+// the neighbouring waves).  Lanes go through their own count, so lanes of a
+// wave finish together whatever part of their neighbourhood lies in which
+// stencil row.
+template <typename R, int DIM, typename F>
+__device__ __forceinline__ void for_list(const View<R>& v, const KC<R>& k, const WaveGeo& g, const uint32_t* jl,
+                                         int w, int n_lane, uint32_t i, const V4<R>& T, bool with_self, F&& visit) {
+  constexpr int CAP = Nb<DIM>::cap;
+  const uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + threadIdx.x;
+  const int nmax = wave_max_i(n_lane);
+  for (int q = 0; q < nmax; ++q) {
+    if (q >= n_lane) continue;
+    const uint32_t e = gl[(size_t)q * 64];
+    const uint32_t rr = e >> 12;
+    const uint32_t j = jl[rr] + (e & 0xfffu);
+    if (j == i && !with_self) continue;
+    const int dz = DIM == 3 ? (int)(rr / 3u) - 1 : 0, dy = (int)(rr % 3u) - 1;
+    const V4<R> sj = to_frame<R>(v.pos[j], k, g.cx_first, dy, dz);
+    R d0, d1, d2;
+    const R r2 = dist2<R, DIM>(T, sj, d0, d1, d2);
+    Nbr<R> nb;
+    nb.j = j;
+    nb.vp = v.vp[j];
+    nb.rm = v.rm[j];
+    visit(nb, d0, d1, d2, r2);
+  }
+}
+
+// the wave's stencil-row bases into LDS (every lane of the wave calls it)
+template <int DIM>
+__device__ __forceinline__ void stage_jlo(uint32_t* jl, const Lists& nb, int w) {
+  constexpr int NR = Nb<DIM>::rows;
+  if ((int)threadIdx.x < NR) jl[threadIdx.x] = nb.jlo[(size_t)w * NR + threadIdx.x];
+  __syncthreads();
 }
 
 __global__ void __launch_bounds__(256) k_row_waves(const uint32_t* cstart, int nx, int64_t nrows, uint32_t* wcount) {
@@ -683,14 +677,6 @@ __global__ void __launch_bounds__(256) k_row_waves_fill(const uint32_t* cstart, 
     wi.pad = 0u;
     table[w0 + q] = wi;
   }
-}
-
-__device__ __forceinline__ int wave_max_i(int x) {
-  for (int off = 32; off > 0; off >>= 1) {
-    int y = __shfl_xor(x, off, 64);
-    x = y > x ? y : x;
-  }
-  return x;
 }
 
 // Candidate test and density: every stencil row's window is staged in LDS
@@ -724,7 +710,7 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
   const R far = R(1e30);
   const R T0 = active ? T.x : far, T1 = active ? T.y : far, T2 = active ? T.z : far;
   uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + lane;
-  int cnt = 0, tb = 0;
+  int cnt = 0;
   bool overflow = false;
   R sum = R(0);
   for (int rr = 0; rr < NR; ++rr) {
@@ -783,20 +769,18 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
       }
       __syncthreads();
     }
-    // the row's entries go to HBM as one block shared by all lanes
+    // the row's entries follow the lane's earlier rows in its flat list
     if (rc > RC || (int)(jhi - jlo) > 4096) overflow = true;
     const int rcc = rc < RC ? rc : RC;
     const int mx = wave_max_i(rcc);
-    const int nw = tb + mx <= CAP ? mx : CAP - tb;
-    if (tb + mx > CAP) overflow = true;
-    for (int t = 0; t < nw; ++t) gl[(size_t)(tb + t) * 64] = rl[t * 64 + lane];
-    v.nb.rcnt[((size_t)w * NR + rr) * 64 + lane] = (uint8_t)(active ? (rcc < nw ? rcc : nw) : 0);
-    if (lane == 0) v.nb.rbase[(size_t)w * NR + rr] = (uint16_t)tb;
-    tb += nw;
-    cnt += active ? rcc : 0;
+    for (int t = 0; t < mx; ++t)
+      if (t < rcc && cnt + t < CAP) gl[(size_t)(cnt + t) * 64] = rl[t * 64 + lane];
+    cnt += rcc;
   }
+  if (cnt > CAP) overflow = true;
   if (overflow && active) set_err(v.err, ERR_NBCAP);
   if (!active) cnt = 0;
+  v.nb.cnt[(size_t)w * 64 + lane] = (uint8_t)(cnt < CAP ? cnt : CAP);
   unsigned long long pairs = 0;
   if (active) {
     const MatT<R>& M = v.mat[iphase(inf)];
@@ -833,8 +817,7 @@ __global__ void __launch_bounds__(64) k_build_density(View<R> v, Params P, KC<R>
 
 template <typename R, int DIM>
 __device__ __forceinline__ void extrapolate_wave(const View<R>& v, const Params& P, const KC<R>& k, int w) {
-  constexpr int CAP = Nb<DIM>::cap, WIN = Win<R>::v;
-  __shared__ V4<R> sp[WIN], svp[WIN], srm[WIN];
+  __shared__ uint32_t jl[Nb<DIM>::rows];
   if (w >= (int)*v.nb.nwaves) return;
   const WaveInfo wi = v.nb.table[w];
   const int lane = threadIdx.x;
@@ -845,11 +828,13 @@ __device__ __forceinline__ void extrapolate_wave(const View<R>& v, const Params&
   if (!__any(need)) return;
   __shared__ MatL<R> smat[kMatLds];
   stage_mats<R>(smat, v, P);
+  stage_jlo<DIM>(jl, v.nb, w);
   const WaveGeo g = wave_geo<R>(v, P, wi);
   const V4<R> T = to_frame<R>(v.pos[i], k, g.cx_first, 0, 0);
+  const int n_lane = need ? (int)v.nb.cnt[(size_t)w * 64 + lane] : 0;
   unsigned long long cr = 0, cw = 0;
   const uint32_t c = extrap_one<R, DIM>(v, k, smat, i, need, [&](bool ws, auto&& f) {
-    for_rows<R, DIM>(v, P, k, g, sp, svp, srm, need, w, i, T, ws, f);
+    for_list<R, DIM>(v, k, g, jl, w, n_lane, i, T, ws, f);
   });
   if (need && kind == KR) cr = c;
   else if (need) cw = c;
@@ -866,8 +851,7 @@ __global__ void __launch_bounds__(64) k_extrapolate_list(View<R> v, Params P, KC
 template <typename R, int DIM, int THERMAL>
 __device__ __forceinline__ void forces_wave(const View<R>& v, const Params& P, const KC<R>& k, int w, int kick,
                                             int heat) {
-  constexpr int CAP = Nb<DIM>::cap, WIN = Win<R>::v;
-  __shared__ V4<R> sp[WIN], svp[WIN], srm[WIN];
+  __shared__ uint32_t jl[Nb<DIM>::rows];
   if (w >= (int)*v.nb.nwaves) return;
   const WaveInfo wi = v.nb.table[w];
   const int lane = threadIdx.x;
@@ -883,10 +867,12 @@ __device__ __forceinline__ void forces_wave(const View<R>& v, const Params& P, c
   if (!__any(need)) return;
   __shared__ MatL<R> smat[kMatLds];
   stage_mats<R>(smat, v, P);
+  stage_jlo<DIM>(jl, v.nb, w);
   const V4<R> T = to_frame<R>(v.pos[i], k, g.cx_first, 0, 0);
+  const int n_lane = need ? (int)v.nb.cnt[(size_t)w * 64 + lane] : 0;
   const double t = (double)(*v.dstep) * P.dt;
   forces_one<R, DIM, THERMAL>(v, P, k, smat, i, need, kick, heat, t, [&](bool ws, auto&& f) {
-    for_rows<R, DIM>(v, P, k, g, sp, svp, srm, need, w, i, T, ws, f);
+    for_list<R, DIM>(v, k, g, jl, w, n_lane, i, T, ws, f);
   });
 }
 
@@ -961,8 +947,7 @@ __global__ void __launch_bounds__(64) k_list_count(View<R> v, Params P, uint32_t
   const int lane = threadIdx.x;
   if (lane >= (int)wi.cnt) return;
   const uint32_t i = wi.p0 + (uint32_t)lane;
-  uint32_t c = 0;
-  for (int rr = 0; rr < NR; ++rr) c += v.nb.rcnt[((size_t)w * NR + rr) * 64 + lane];
+  const uint32_t c = v.nb.cnt[(size_t)w * 64 + lane];
   out[v.id[i]] = c > 0 ? c - 1 : 0u;
 }
 
@@ -978,14 +963,11 @@ __global__ void __launch_bounds__(64) k_list_fill(View<R> v, Params P, const uin
   const uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + lane;
   const uint32_t* jlo = v.nb.jlo + (size_t)w * NR;
   uint64_t o = off[v.id[i]];
-  for (int rr = 0; rr < NR; ++rr) {
-    const int tb = v.nb.rbase[(size_t)w * NR + rr];
-    const int c = v.nb.rcnt[((size_t)w * NR + rr) * 64 + lane];
-    for (int q = 0; q < c; ++q) {
-      const uint32_t e = gl[(size_t)(tb + q) * 64];
-      const uint32_t j = jlo[rr] + (e & 0xfffu);
-      if (j != i) ids[o++] = v.id[j];
-    }
+  const int c = v.nb.cnt[(size_t)w * 64 + lane];
+  for (int q = 0; q < c; ++q) {
+    const uint32_t e = gl[(size_t)q * 64];
+    const uint32_t j = jlo[e >> 12] + (e & 0xfffu);
+    if (j != i) ids[o++] = v.id[j];
   }
 }
 
@@ -1892,26 +1874,24 @@ __global__ void __launch_bounds__(64) k_ps_nearest(View<R> v, Params P, KC<R> k)
   R br2 = R(0);
   int bb = 0;
   uint32_t bid = 0u;
-  for (int rr = 0; rr < NR; ++rr) {
+  const int c = v.nb.cnt[(size_t)w * 64 + lane];
+  for (int t = 0; t < c; ++t) {
+    const uint32_t e = gl[(size_t)t * 64];
+    const int rr = (int)(e >> 12);
     const int dz = DIM == 3 ? rr / 3 - 1 : 0, dy = rr % 3 - 1;
-    const int tb = v.nb.rbase[(size_t)w * NR + rr];
-    const int c = v.nb.rcnt[((size_t)w * NR + rr) * 64 + lane];
-    const uint32_t jlo = v.nb.jlo[(size_t)w * NR + rr];
-    for (int t = 0; t < c; ++t) {
-      const uint32_t j = jlo + ((uint32_t)gl[(size_t)(tb + t) * 64] & 0xfffu);
-      if (j == i) continue;
-      const uint32_t ij = v.info[j];
-      if (ikind(ij) != KR) continue;
-      R d0, d1, d2;
-      const R r2 = dist2<R, DIM>(T, to_frame<R>(v.pos[j], k, g.cx_first, dy, dz), d0, d1, d2);
-      const int bj = ibody(ij);
-      const uint32_t idj = v.id[j];
-      if (!found || r2 < br2 || (r2 == br2 && (bj < bb || (bj == bb && idj < bid)))) {
-        found = true;
-        br2 = r2;
-        bb = bj;
-        bid = idj;
-      }
+    const uint32_t j = v.nb.jlo[(size_t)w * NR + rr] + (e & 0xfffu);
+    if (j == i) continue;
+    const uint32_t ij = v.info[j];
+    if (ikind(ij) != KR) continue;
+    R d0, d1, d2;
+    const R r2 = dist2<R, DIM>(T, to_frame<R>(v.pos[j], k, g.cx_first, dy, dz), d0, d1, d2);
+    const int bj = ibody(ij);
+    const uint32_t idj = v.id[j];
+    if (!found || r2 < br2 || (r2 == br2 && (bj < bb || (bj == bb && idj < bid)))) {
+      found = true;
+      br2 = r2;
+      bb = bj;
+      bid = idj;
     }
   }
   if (found) {
@@ -1943,16 +1923,13 @@ __global__ void __launch_bounds__(256) k_ps_components(View<R> v, Params P, cons
       const int lane = (int)(i - v.nb.table[w].p0);
       const uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + lane;
       uint32_t m = v.ps.label[i];
-      for (int rr = 0; rr < NR; ++rr) {
-        const int tb = v.nb.rbase[(size_t)w * NR + rr];
-        const int c = v.nb.rcnt[((size_t)w * NR + rr) * 64 + lane];
-        const uint32_t jlo = v.nb.jlo[(size_t)w * NR + rr];
-        for (int t = 0; t < c; ++t) {
-          const uint32_t j = jlo + ((uint32_t)gl[(size_t)(tb + t) * 64] & 0xfffu);
-          if (j == i || v.ps.flag[j] != 2 || v.ps.target[j] >= 0) continue;
-          const uint32_t lj = v.ps.label[j];
-          if (lj < m) m = lj;
-        }
+      const int c = v.nb.cnt[(size_t)w * 64 + lane];
+      for (int t = 0; t < c; ++t) {
+        const uint32_t e = gl[(size_t)t * 64];
+        const uint32_t j = v.nb.jlo[(size_t)w * NR + (e >> 12)] + (e & 0xfffu);
+        if (j == i || v.ps.flag[j] != 2 || v.ps.target[j] >= 0) continue;
+        const uint32_t lj = v.ps.label[j];
+        if (lj < m) m = lj;
       }
       if (m < v.ps.label[i]) {
         v.ps.label[i] = m;
