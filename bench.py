@@ -58,9 +58,57 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-side", type=int, default=100)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--serve-scenes", type=int, default=24,
+                    help="scenes of the serving run (continuous batching); 0 skips it")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates HBM byte counters)")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "forces_traffic_3d_column_64_spheres.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2103_07925_amd", "csrc", "sph_kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per force-kernel launch from the committed counter summary,
+    or None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        txt = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", txt)
+    b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not b:
+        return None
+    if hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest() != m.group(1):
+        return None
+    return float(b.group(1))
+
+
+def serving_run(n_scenes, seed):
+    """A short continuous-batching run: n_scenes requests of 1e4-1e5
+    particles (2D box, 3D column, thermal grains), 50 steps each, arrivals
+    at 0.8 of the capacity measured on the same requests, pool budget a
+    third of their total footprint."""
+    from paper_2103_07925_amd import serve as SV
+    be = SV.GpuBackend()
+    reqs = SV.make_requests(n_scenes, seed=seed, n_range=(1e4, 1e5), steps=50)
+    total = sum(be.footprint(r) for r in reqs)
+    budget = max(total // 3, max(be.footprint(r) for r in reqs))
+    cal = SV.Server(be, budget, 128).run(reqs)
+    rate = 0.8 * len(reqs) / cal["makespan_s"]
+    rng = np.random.default_rng(seed + 1)
+    t = 0.0
+    for r in reqs:
+        t += float(rng.exponential(1.0 / rate))
+        r.arrival = t
+    rep = SV.Server(be, budget, 128).run(reqs)
+    rep.update({"budget_bytes": int(budget), "total_footprint_bytes": int(total), "arrival_rate_per_s": rate,
+                "capacity_pair_interactions_per_s": cal["pair_interactions_per_s"],
+                "requests": f"{n_scenes} scenes, 1e4-1e5 particles log-uniform, 50 steps each, FP32 sweep"})
+    return rep
 
 
 def calibrate_copy(mib):
@@ -183,7 +231,7 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / PEAK_FP32_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "pairs_per_launch": int(force_pairs),
             "flops_per_pair": FLOPS_FORCE_PAIR,
             "avg_launch_ms": forces_ms,
@@ -193,6 +241,10 @@ def main():
         "fp64_path": {"value": value64, "unit": UNIT, "steps": args.fp64_steps,
                       "fp32_speedup": value / value64},
     }
+
+    if args.serve_scenes > 0:
+        out["serving"] = serving_run(args.serve_scenes, args.seed)
+        torch.cuda.empty_cache()
 
     # ---- CPU baseline: the oracle on a bounded sample ------------------------
     if not args.no_cpu_baseline:

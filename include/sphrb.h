@@ -126,7 +126,11 @@ typedef struct {
   int64_t pairs_wall;          /* last evaluation: fluid neighbours of wall particles */
   uint32_t device_error;       /* SPH_ERR_* bits */
   uint32_t pad;
-  double mass, momentum[3], kinetic;   /* FP64 global checks (particles + bodies) */
+  double mass, momentum[3], kinetic;   /* FP64 global checks: fluid particles + active bodies
+                                          (bodies: translation and rotation) */
+  double potential;            /* energy of the body force, -sum m b.x (fluid + bodies) */
+  int64_t n_melted;            /* phase switches since creation: rigid -> fluid */
+  int64_t n_solidified;        /* and fluid -> rigid */
 } sph_stats;
 
 int sph_abi_version(void);

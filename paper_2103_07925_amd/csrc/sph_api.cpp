@@ -285,7 +285,7 @@ void carve(Carver& cv, sph_scene* s, const Params& P, int64_t nmat) {
   s->woff = cv.take<uint32_t>((size_t)P.nrows + 1);
   s->wbsum = cv.take<uint32_t>((size_t)(P.nrows + 1023) / 1024 + 1);
   s->nb.nwaves = s->woff + P.nrows;
-  s->gpart = cv.take<double>(5 * kGlobalBlocks);
+  s->gpart = cv.take<double>(6 * kGlobalBlocks);
   s->gout = cv.take<double>(8);
   s->dyn = cv.take<uint32_t>(4);
   s->dstep = cv.take<unsigned long long>(1);
@@ -1309,10 +1309,12 @@ int sph_scene_read_stats(sph_scene* s, sph_stats* o) {
   HIP_TRY(hipStreamSynchronize(s->stream));
   unsigned long long pr[6];
   uint32_t err = 0;
-  double g[5];
+  double g[6];
+  uint32_t dyn[4];
   HIP_TRY(hipMemcpy(pr, s->pairs, sizeof(pr), hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(&err, s->err, 4, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(g, s->gout, sizeof(g), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(dyn, s->dyn, sizeof(dyn), hipMemcpyDeviceToHost));
   int64_t nrig = 0;
   int nbod = 0;
   if (int e = dyn_counts(s, &nrig, &nbod)) return e;
@@ -1334,7 +1336,7 @@ int sph_scene_read_stats(sph_scene* s, sph_stats* o) {
   o->pairs_wall = (int64_t)pr[4];
   o->device_error = err;
   // fluid part from the device reduction, bodies added here
-  double mass = g[0], mom[3] = {g[1], g[2], g[3]}, ke = g[4];
+  double mass = g[0], mom[3] = {g[1], g[2], g[3]}, ke = g[4], pe = g[5];
   if (nbod > 0) {
     std::vector<Body> b(nbod);
     HIP_TRY(hipMemcpy(b.data(), s->bodies, sizeof(Body) * nbod, hipMemcpyDeviceToHost));
@@ -1343,11 +1345,25 @@ int sph_scene_read_stats(sph_scene* s, sph_stats* o) {
       mass += B.m;
       for (int a = 0; a < 3; ++a) mom[a] += B.m * B.u[a];
       ke += 0.5 * B.m * (B.u[0] * B.u[0] + B.u[1] * B.u[1] + B.u[2] * B.u[2]);
+      // rotational part, w . (R I^b R^T) w / 2
+      if (P.dim == 3) {
+        double R[9], wb[3], Iwb[3];
+        quat_rot(B.q, R);
+        for (int a = 0; a < 3; ++a) wb[a] = R[a] * B.w[0] + R[3 + a] * B.w[1] + R[6 + a] * B.w[2];
+        for (int a = 0; a < 3; ++a) Iwb[a] = B.Ib[3 * a] * wb[0] + B.Ib[3 * a + 1] * wb[1] + B.Ib[3 * a + 2] * wb[2];
+        ke += 0.5 * (wb[0] * Iwb[0] + wb[1] * Iwb[1] + wb[2] * Iwb[2]);
+      } else {
+        ke += 0.5 * B.Ib[8] * B.w[2] * B.w[2];
+      }
+      pe -= B.m * (B.b[0] * B.r[0] + B.b[1] * B.r[1] + B.b[2] * B.r[2]);
     }
   }
   o->mass = mass;
   for (int a = 0; a < 3; ++a) o->momentum[a] = mom[a];
   o->kinetic = ke;
+  o->potential = pe;
+  o->n_melted = P.pswitch ? (int64_t)dyn[2] : 0;
+  o->n_solidified = P.pswitch ? (int64_t)dyn[3] : 0;
   return SPH_OK;
 }
 

@@ -1563,36 +1563,44 @@ __global__ void __launch_bounds__(256) k_rigid_aw(const Body* bodies, const int3
 // global FP64 checks: mass, momentum, kinetic energy of fluid particles
 // ---------------------------------------------------------------------------
 
+// fluid mass, momentum, kinetic energy and potential energy of the body
+// force, -m b.x
 template <typename R>
 __global__ void __launch_bounds__(256) k_global_partials(View<R> v, Params P, double* part) {
-  DD acc[5];
-  for (int q = 0; q < 5; ++q) acc[q].hi = acc[q].lo = 0.0;
+  DD acc[6];
+  for (int q = 0; q < 6; ++q) acc[q].hi = acc[q].lo = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.n; i += (int64_t)gridDim.x * blockDim.x) {
-    if (ikind(v.info[i]) != KF) continue;
+    const uint32_t inf = v.info[i];
+    if (ikind(inf) != KF) continue;
     const double m = (double)v.m[i];
     const V4<R> u = v.u[i];
     const double ux = u.x, uy = u.y, uz = u.z;
+    double x[3];
+    get_pos<R>(P, v, i, x);
+    const MatT<R>& M = v.mat[iphase(inf)];
+    const double bx = (double)M.b[0] * x[0] + (double)M.b[1] * x[1] + (P.dim == 3 ? (double)M.b[2] * x[2] : 0.0);
     dd_add(acc[0], m);
     dd_add(acc[1], m * ux);
     dd_add(acc[2], m * uy);
     dd_add(acc[3], m * uz);
     dd_add(acc[4], 0.5 * m * (ux * ux + uy * uy + uz * uz));
+    dd_add(acc[5], -(m * bx));
   }
-  double out[5];
-  block_reduce_dd<5>(acc, out);
+  double out[6];
+  block_reduce_dd<6>(acc, out);
   if (threadIdx.x == 0)
-    for (int q = 0; q < 5; ++q) part[5 * blockIdx.x + q] = out[q];
+    for (int q = 0; q < 6; ++q) part[6 * blockIdx.x + q] = out[q];
 }
 
 __global__ void __launch_bounds__(256) k_global_final(const double* part, int nb, double* out) {
-  DD acc[5];
-  for (int q = 0; q < 5; ++q) acc[q].hi = acc[q].lo = 0.0;
+  DD acc[6];
+  for (int q = 0; q < 6; ++q) acc[q].hi = acc[q].lo = 0.0;
   for (int b = threadIdx.x; b < nb; b += blockDim.x)
-    for (int q = 0; q < 5; ++q) dd_add(acc[q], part[5 * b + q]);
-  double o[5];
-  block_reduce_dd<5>(acc, o);
+    for (int q = 0; q < 6; ++q) dd_add(acc[q], part[6 * b + q]);
+  double o[6];
+  block_reduce_dd<6>(acc, o);
   if (threadIdx.x == 0)
-    for (int q = 0; q < 5; ++q) out[q] = o[q];
+    for (int q = 0; q < 6; ++q) out[q] = o[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -1824,6 +1832,9 @@ __global__ void __launch_bounds__(256) k_ps_flags(View<R> v, Params P) {
     any = f != 0;
   }
   wave_count(&v.ps.ctr[0], any);
+  const uint8_t fl = i < P.n ? v.ps.flag[i] : (uint8_t)0;
+  wave_count(&v.dyn[2], fl == 1);     // melted, cumulative
+  wave_count(&v.dyn[3], fl == 2);     // solidifying, cumulative
 }
 
 // melting: the particle keeps the velocity and the acceleration of its

@@ -65,7 +65,8 @@ class sph_stats(C.Structure):
                 ("pairs_last", C.c_int64), ("pairs_total", C.c_int64), ("pairs_fluid", C.c_int64),
                 ("pairs_rigid", C.c_int64), ("pairs_wall", C.c_int64), ("device_error", C.c_uint32),
                 ("pad", C.c_uint32), ("mass", C.c_double), ("momentum", C.c_double * 3),
-                ("kinetic", C.c_double)]
+                ("kinetic", C.c_double), ("potential", C.c_double), ("n_melted", C.c_int64),
+                ("n_solidified", C.c_int64)]
 
 
 _lib = None

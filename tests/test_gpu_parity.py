@@ -277,3 +277,65 @@ def test_checkpoint_resume_is_bitwise(B, case):
     assert np.array_equal(np.concatenate(ref.flags()), np.concatenate(r.flags()))
     s1, s2 = ref.stats(), r.stats()
     assert (s1.step, s1.pairs_total, s1.n_bodies) == (s2.step, s2.pairs_total, s2.n_bodies)
+
+
+# ---- global FP64 checks ------------------------------------------------------
+
+def _oracle_globals(sc, o):
+    kind = o.get_int(O.I_KIND)
+    ph = o.get_int(O.I_PHASE)
+    fl = kind == S.FLUID
+    m = o.get(O.F_M)[fl]
+    u = o.get(O.F_U)[fl]
+    x = o.get(O.F_X)[fl]
+    b = np.array([sc.materials[p].b for p in ph[fl]], np.float64)
+    bo = o.bodies()
+    act = bo[:, 32] > 0
+    bo = bo[act]
+    mass = m.sum() + bo[:, 0].sum()
+    mom = (m[:, None] * u).sum(0) + (bo[:, 0:1] * bo[:, 8:11]).sum(0)
+    ke = 0.5 * (m * (u * u).sum(1)).sum() + 0.5 * (bo[:, 0] * (bo[:, 8:11] ** 2).sum(1)).sum()
+    for rec in bo:
+        w = rec[11:14]
+        if sc.dim == 3:
+            I = np.array([[rec[26], rec[29], rec[30]], [rec[29], rec[27], rec[31]], [rec[30], rec[31], rec[28]]])
+            ke += 0.5 * w @ I @ w
+        else:
+            ke += 0.5 * rec[28] * w[2] ** 2
+    pe = -(m * (b * x).sum(1)).sum()
+    # body force of a body: that of its particles' phase
+    body = o.get_int(O.I_BODY)
+    for k, rec in zip(np.nonzero(act)[0], bo):
+        p = ph[(kind == S.RIGID) & (body == k)][0]
+        pe -= rec[0] * np.dot(sc.materials[p].b[:sc.dim], rec[1:1 + sc.dim])
+    return mass, mom, ke, pe
+
+
+@pytest.mark.parametrize("case", ["c1", "3d", "switch"])
+def test_global_checks_match_the_oracle_fields(B, case):
+    if case == "c1":
+        sc = S.config_c1(seed=1)
+    elif case == "3d":
+        sc = small_3d(seed=2)
+        sc.bodies[0].w = (0.3, -0.2, 0.5)
+    else:
+        sc = _scripted_switch_scene()
+    o, g = run_pair(sc, B.SPH_FP64, 6)
+    mass, mom, ke, pe = _oracle_globals(sc, o)
+    st = g.stats()
+    assert abs(st.mass - mass) <= 1e-12 * mass
+    scale = max(np.abs(mom).max(), 1e-30)
+    assert np.max(np.abs(np.array(st.momentum) - mom)) <= 1e-10 * scale + 1e-15 * mass
+    assert abs(st.kinetic - ke) <= 1e-10 * max(ke, 1e-30)
+    assert abs(st.potential - pe) <= 1e-10 * max(abs(pe), 1e-30)
+    if case == "switch":
+        o0 = O.OracleScene(sc)
+        k0 = o0.get_int(O.I_KIND)
+        g1 = B.SphScene(sc, precision=B.SPH_FP64)
+        g1.step(1)
+        o0.step(1)
+        k1 = o0.get_int(O.I_KIND)
+        s1 = g1.stats()
+        assert s1.n_melted == int(np.sum((k0 == S.RIGID) & (k1 == S.FLUID)))
+        assert s1.n_solidified == int(np.sum((k0 == S.FLUID) & (k1 == S.RIGID)))
+        assert s1.n_melted > 0 and s1.n_solidified > 0
