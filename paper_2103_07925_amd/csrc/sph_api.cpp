@@ -84,7 +84,7 @@ struct sph_scene {
   uint32_t* info[2];
   int32_t* aux[2];
   int ip, iu, iT;
-  void *rho, *p, *pw, *uw, *dTdt, *vp, *rm;
+  void *rho, *p, *pw, *uw, *dTdt, *vp, *rm, *pa;
   SortBufs sb;
   uint32_t* cstart;
   V4<double> *s_rb, *s_rk, *s_f, *s_aw, *s_x;
@@ -248,6 +248,7 @@ void carve(Carver& cv, sph_scene* s, const Params& P, int64_t nmat) {
   s->uw = cv.take<V4<R>>(n);
   s->dTdt = cv.take<R>(n);
   s->vp = cv.take<V4<R>>(n);
+  s->pa = cv.take<V4<R>>(n);
   s->rm = cv.take<V4<R>>(n);
   s->sb.key = cv.take<uint32_t>(n);
   s->sb.rank = cv.take<uint32_t>(n);
@@ -280,6 +281,7 @@ void carve(Carver& cv, sph_scene* s, const Params& P, int64_t nmat) {
   s->nb.table = cv.take<WaveInfo>((size_t)P.max_waves);
   s->nb.ent = cv.take<uint16_t>((size_t)P.max_waves * cap * 64);
   s->nb.cnt = cv.take<uint8_t>((size_t)P.max_waves * 64);
+  s->nb.split = cv.take<uint8_t>((size_t)P.max_waves * 64);
   s->nb.jlo = cv.take<uint32_t>((size_t)P.max_waves * nsr);
   s->wcount = cv.take<uint32_t>((size_t)P.nrows);
   s->woff = cv.take<uint32_t>((size_t)P.nrows + 1);
@@ -341,6 +343,7 @@ int make_params(const sph_scene_desc* d, Params& P, double* m_min) {
     P.ncells *= P.nc[a];
   }
   if (P.ncells > 0x7fffffffLL) return fail(SPH_E_INVALID, "cell grid too large");
+  if (P.nc[0] > 65535) return fail(SPH_E_INVALID, "more than 65535 cells along x");
   const double sg = sigma_d(d->dim);
   P.wnorm = sg / powi(P.h, d->dim);
   P.dnorm = -5.0 * sg / powi(P.h, d->dim + 1);
@@ -434,6 +437,7 @@ View<R> make_view(sph_scene* s, int ip, int iu, int iT) {
   v.uw = (V4<R>*)s->uw;
   v.dTdt = (R*)s->dTdt;
   v.vp = (V4<R>*)s->vp;
+  v.pa = (V4<R>*)s->pa;
   v.rm = (V4<R>*)s->rm;
   v.cstart = s->cstart;
   v.s_rb = s->s_rb;
@@ -713,6 +717,7 @@ int create_impl(const sph_scene_desc* d, sph_scene* s) {
     o.inv_cp = (R)(M.cp != 0.0 ? 1.0 / M.cp : 0.0);
     for (int ax = 0; ax < 3; ++ax) o.b[ax] = (R)(ax < d->dim ? M.b[ax] : 0.0);
     o.switch_to = M.switch_to;
+    o.mass = (R)(M.rho0 * P.vol0);
     o.dirichlet = M.dirichlet;
   }
   // bodies

@@ -38,6 +38,7 @@ enum : uint32_t { ERR_ESCAPE = 1, ERR_CELL = 2, ERR_NONFINITE = 4, ERR_COINCIDEN
 template <typename R>
 struct MatT {
   R rho0, p0, nu, cp, kappa, eta, T_t, inv_rho0, inv_p0, inv_cp;
+  R mass;   // particle mass of the phase, rho0 dx^d (as set at creation)
   R b[3];
   int32_t switch_to, dirichlet;
 };
@@ -83,6 +84,8 @@ struct Lists {
   uint32_t* nwaves;
   uint16_t* ent;
   uint8_t* cnt;        // entries of every lane (self included), [wave][lane]
+  uint8_t* split;      // entries in canonical order from the front; wall and rigid
+                       // lanes: their fluid neighbours (the rest from the end)
   uint32_t* jlo;
 };
 
@@ -141,6 +144,8 @@ struct View {
   R* dTdt;
   V4<R>* vp;   // neighbour record: (u, p) of fluid, (u~_w, p_w) of wall / rigid particles
   V4<R>* rm;   // neighbour record: (rho, m, info bits, T)
+  V4<R>* pa;   // FP32 neighbour record: cell offsets x, y, z and packed cell x /
+               // kind / phase / mass-not-of-phase bits (see pack_pa)
   // cells
   uint32_t* cstart;   // C + 1
   // rigid slots (body-sorted)

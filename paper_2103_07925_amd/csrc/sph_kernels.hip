@@ -230,13 +230,14 @@ __device__ __forceinline__ uint32_t r_to_info(double v) { return (uint32_t)v; }
 constexpr int kMatLds = 16;
 template <typename R>
 struct MatL {
-  R eta, kappa, rho0, p0, inv_p0, b0, b1, b2, dir;
+  R eta, kappa, rho0, p0, inv_p0, b0, b1, b2, dir, mass;
 };
 template <typename R>
 __device__ __forceinline__ MatL<R> mat_from(const MatT<R>& M) {
   MatL<R> o;
   o.eta = M.eta; o.kappa = M.kappa; o.rho0 = M.rho0; o.p0 = M.p0; o.inv_p0 = M.inv_p0;
   o.b0 = M.b[0]; o.b1 = M.b[1]; o.b2 = M.b[2]; o.dir = M.dirichlet ? R(1) : R(0);
+  o.mass = M.mass;
   return o;
 }
 // fills the table; every thread of the workgroup calls it (it synchronises)
@@ -457,7 +458,7 @@ __device__ __forceinline__ void forces_one(const View<R>& v, const Params& P, co
       acc0 = acc0 + F[0];
       acc1 = acc1 + F[1];
       if (DIM == 3) acc2 = acc2 + F[2];
-    } else if (P.contact && r2 < k.dx2 && (kj == KW || ibody(ij) != body_i)) {
+    } else if (P.contact && r2 < k.dx2 && (kj == KW || ibody(v.info[nb.j]) != body_i)) {
       const V4<R> uj = v.u[nb.j];
       R e0, e1, e2 = R(0), en;
       if constexpr (IsExact<R>::v) {
@@ -615,7 +616,9 @@ __device__ __forceinline__ int wave_max_i(int x) {
   return x;
 }
 
-// Walk one lane's list: entry q of lane l sits at [wave][q][l], so the
+// Walk one lane's list: entry q of lane l sits at [wave][q][l] (entries
+// from split on at [wave][CAP - 1 - (q - split)][l]: the non-fluid
+// neighbours of wall and rigid lanes, stored from the end), so the
 // wave reads one 128-byte line per step; the entry gives the stencil row
 // (bits 12-15) and the offset from that row's first candidate, whose index
 // jl[] holds (LDS).  The neighbour's position and records are read straight
@@ -623,26 +626,56 @@ __device__ __forceinline__ int wave_max_i(int x) {
 // the neighbouring waves).  Lanes go through their own count, so lanes of a
 // wave finish together whatever part of their neighbourhood lies in which
 // stencil row.
-template <typename R, int DIM, typename F>
-__device__ __forceinline__ void for_list(const View<R>& v, const KC<R>& k, const WaveGeo& g, const uint32_t* jl,
-                                         int w, int n_lane, uint32_t i, const V4<R>& T, bool with_self, F&& visit) {
+// FP32 sweeps without heat read two 16-byte records per neighbour: pa
+// (cell offsets, packed cell x / kind / phase) and vp; a fluid neighbour's
+// density is recovered from its pressure by the inverse equation of state
+// and its mass is that of its phase, unless a flag says otherwise (a phase
+// switch kept the old mass), in which case its full rm record is read.
+template <typename R, int DIM, bool PACKED, typename F>
+__device__ __forceinline__ void for_list(const View<R>& v, const KC<R>& k, const MatL<R>* sm, const WaveGeo& g,
+                                         const uint32_t* jl, int w, int n_lane, int split, uint32_t i,
+                                         const V4<R>& T, bool with_self, F&& visit) {
   constexpr int CAP = Nb<DIM>::cap;
   const uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + threadIdx.x;
   const int nmax = wave_max_i(n_lane);
   for (int q = 0; q < nmax; ++q) {
     if (q >= n_lane) continue;
-    const uint32_t e = gl[(size_t)q * 64];
+    const int at = q < split ? q : CAP - 1 - (q - split);
+    // streamed once: kept out of the L1, which holds the gathered records
+    const uint32_t e = __builtin_nontemporal_load(gl + (size_t)at * 64);
     const uint32_t rr = e >> 12;
     const uint32_t j = jl[rr] + (e & 0xfffu);
     if (j == i && !with_self) continue;
     const int dz = DIM == 3 ? (int)(rr / 3u) - 1 : 0, dy = (int)(rr % 3u) - 1;
-    const V4<R> sj = to_frame<R>(v.pos[j], k, g.cx_first, dy, dz);
-    R d0, d1, d2;
-    const R r2 = dist2<R, DIM>(T, sj, d0, d1, d2);
     Nbr<R> nb;
     nb.j = j;
-    nb.vp = v.vp[j];
-    nb.rm = v.rm[j];
+    V4<R> pj;
+    if constexpr (PACKED && !IsExact<R>::v) {
+      const V4<R> a = v.pa[j];
+      const uint32_t pk = __float_as_uint(a.w);
+      pj.x = a.x;
+      pj.y = a.y;
+      pj.z = a.z;
+      pj.w = (R)(pk & 0xffffu);
+      nb.vp = v.vp[j];
+      if ((pk >> 26) & 1u) {
+        nb.rm = v.rm[j];
+      } else {
+        const uint32_t kj = (pk >> 16) & 3u, ph = (pk >> 18) & 0xffu;
+        const MatL<R> M = mat_of<R>(sm, v, ph);
+        nb.rm.x = kj == KF ? inv_eos<R>(M, nb.vp.w) : M.rho0;
+        nb.rm.y = M.mass;
+        nb.rm.z = info_to_r(mkinfo(kj, ph, 0u, -1), R(0));
+        nb.rm.w = R(0);
+      }
+    } else {
+      pj = v.pos[j];
+      nb.vp = v.vp[j];
+      nb.rm = v.rm[j];
+    }
+    const V4<R> sj = to_frame<R>(pj, k, g.cx_first, dy, dz);
+    R d0, d1, d2;
+    const R r2 = dist2<R, DIM>(T, sj, d0, d1, d2);
     visit(nb, d0, d1, d2, r2);
   }
 }
@@ -693,7 +726,7 @@ template <int DIM> struct RowCap { static constexpr int v = DIM == 3 ? 64 : 32; 
 template <typename R, int DIM>
 __device__ __forceinline__ void build_density_wave(const View<R>& v, const Params& P, const KC<R>& k, int w) {
   constexpr int CAP = Nb<DIM>::cap, NR = Nb<DIM>::rows, WIN = Win<R>::v, RC = RowCap<DIM>::v;
-  __shared__ V4<R> stg[WIN];
+  __shared__ V4<R> stg[WIN + 4];
   __shared__ uint16_t rl[RC * 64];
   if (w >= (int)*v.nb.nwaves) return;
   const WaveInfo wi = v.nb.table[w];
@@ -709,78 +742,100 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
   // inactive lanes test against an unreachable point and never hit
   const R far = R(1e30);
   const R T0 = active ? T.x : far, T1 = active ? T.y : far, T2 = active ? T.z : far;
+  // wall and rigid lanes keep their fluid neighbours first (in canonical
+  // order), the others from the end of their block backwards
+  const bool part = active && kind != KF;
+  // the lane's own cells of every stencil row: cx - 1 .. cx + 1
+  const int cxl = active ? (int)(v.cell[i] - wi.row * (uint32_t)nx) : g.cx_first;
+  const int ca = cxl - 1 < 0 ? 0 : cxl - 1, cb = cxl + 1 > nx - 1 ? nx - 1 : cxl + 1;
   uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + lane;
-  int cnt = 0;
+  int nf = 0, nb = 0;
   bool overflow = false;
   R sum = R(0);
   for (int rr = 0; rr < NR; ++rr) {
     const int dz = DIM == 3 ? rr / 3 - 1 : 0, dy = rr % 3 - 1;
     const int yy = g.cy + dy, zz = g.cz + dz;
-    uint32_t jlo = 0u, jhi = 0u;
+    uint32_t jlo = 0u, jhi = 0u, llo = 0u, lhi = 0u;
     if (yy >= 0 && yy < ny && zz >= 0 && zz < nz) {
       const uint32_t rb2 = (uint32_t)((zz * ny + yy) * nx);
       jlo = v.cstart[rb2 + g.clo];
       jhi = v.cstart[rb2 + g.chi + 1];
+      llo = v.cstart[rb2 + ca] - jlo;
+      lhi = v.cstart[rb2 + cb + 1] - jlo;
     }
+    if (!active) lhi = llo;
     if (lane == rr) v.nb.jlo[(size_t)w * NR + rr] = jlo;
-  int rc = 0;
+    int rc = 0;
     for (uint32_t seg = jlo; seg < jhi; seg += (uint32_t)WIN) {
       const int ns = (int)(jhi - seg < (uint32_t)WIN ? jhi - seg : (uint32_t)WIN);
-      for (int q = lane; q < ns; q += 64) stg[q] = to_frame<R>(v.pos[seg + q], k, g.cx_first, dy, dz);
+      for (int q = lane; q < ns + 4; q += 64) {
+        V4<R> sq;
+        if (q < ns) {
+          sq = to_frame<R>(v.pos[seg + q], k, g.cx_first, dy, dz);
+          sq.w = info_to_r(v.info[seg + q], R(0));
+        } else {
+          sq.x = sq.y = sq.z = -far;    // padding: never a neighbour
+          sq.w = R(0);
+        }
+        stg[q] = sq;
+      }
       __syncthreads();
       const int rc0 = rc;
-      const uint32_t tag = ((uint32_t)rr << 12) | (seg - jlo);
-      int q = 0;
-      for (; q + 4 <= ns; q += 4) {
-        const V4<R> s0 = stg[q], s1 = stg[q + 1], s2 = stg[q + 2], s3 = stg[q + 3];
+      const uint32_t so = seg - jlo;
+      const uint32_t tag = ((uint32_t)rr << 12) | so;
+      // this lane's candidates inside the segment: [qa, qb); every lane
+      // runs over the same number of candidates from qs <= qa, so that it
+      // stays inside the segment -- the extra ones lie in cells out of the
+      // lane's reach (at least one cell edge >= r_c away in x) and never hit
+      const int qa = (int)((llo > so ? llo : so) - so);
+      int qb = (int)((lhi < so + (uint32_t)ns ? lhi : so + (uint32_t)ns) - so);
+      if (qb < qa) qb = qa;
+      if (jhi - jlo > 4096u) qb = qa;     // entries hold 12-bit offsets: an error, below
+      const int mlen = wave_max_i(qb - qa);
+      const int qs = qa < ns - mlen ? qa : ns - mlen;
+      const V4<R>* sp = stg + qs;
+      uint32_t e = tag + (uint32_t)qs;
+      for (int t = 0; t < mlen; t += 4) {
         R e0, e1, e2;
-        const R a0 = dist2<R, DIM>(V4<R>{T0, T1, T2, R(0)}, s0, e0, e1, e2);
-        const R a1 = dist2<R, DIM>(V4<R>{T0, T1, T2, R(0)}, s1, e0, e1, e2);
-        const R a2 = dist2<R, DIM>(V4<R>{T0, T1, T2, R(0)}, s2, e0, e1, e2);
-        const R a3 = dist2<R, DIM>(V4<R>{T0, T1, T2, R(0)}, s3, e0, e1, e2);
-        const int slot0 = rc < RC ? rc : RC - 1;
-        rl[slot0 * 64 + lane] = (uint16_t)(tag + (uint32_t)q);
-        rc += a0 < k.rc2 ? 1 : 0;
-        const int slot1 = rc < RC ? rc : RC - 1;
-        rl[slot1 * 64 + lane] = (uint16_t)(tag + (uint32_t)q + 1u);
-        rc += a1 < k.rc2 ? 1 : 0;
-        const int slot2 = rc < RC ? rc : RC - 1;
-        rl[slot2 * 64 + lane] = (uint16_t)(tag + (uint32_t)q + 2u);
-        rc += a2 < k.rc2 ? 1 : 0;
-        const int slot3 = rc < RC ? rc : RC - 1;
-        rl[slot3 * 64 + lane] = (uint16_t)(tag + (uint32_t)q + 3u);
-        rc += a3 < k.rc2 ? 1 : 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const R a0 = dist2<R, DIM>(V4<R>{T0, T1, T2, R(0)}, sp[t + u], e0, e1, e2);
+          const int slot = rc < RC ? rc : RC - 1;
+          rl[slot * 64 + lane] = (uint16_t)(e + (uint32_t)u);
+          rc += a0 < k.rc2 ? 1 : 0;
+        }
+        e += 4u;
       }
-      for (; q < ns; ++q) {
-        R e0, e1, e2;
-        const R a0 = dist2<R, DIM>(V4<R>{T0, T1, T2, R(0)}, stg[q], e0, e1, e2);
-        const int slot0 = rc < RC ? rc : RC - 1;
-        rl[slot0 * 64 + lane] = (uint16_t)(tag + (uint32_t)q);
-        rc += a0 < k.rc2 ? 1 : 0;
-      }
-      if (dens) {
-        const int t1 = rc < RC ? rc : RC;
-        for (int t = rc0; t < t1; ++t) {
-          const int qq = (int)((uint32_t)rl[t * 64 + lane] & 0xfffu) - (int)(seg - jlo);
+      // density of this segment's hits, and the hits into the lane's list
+      const int t1 = rc < RC ? rc : RC;
+      const int mh = wave_max_i(t1 - rc0);
+      for (int t = rc0; t < rc0 + mh; ++t) {
+        if (t >= t1) continue;
+        const uint32_t e = rl[t * 64 + lane];
+        const V4<R> sj = stg[(int)(e & 0xfffu) - (int)so];
+        if (dens) {
           R d0, d1, d2;
-          const R r2 = dist2<R, DIM>(T, stg[qq], d0, d1, d2);
+          const R r2 = dist2<R, DIM>(T, sj, d0, d1, d2);
           sum = sum + kern_w<R>(ksqrt(r2), k);
         }
+        if (nf + nb >= CAP) {
+          overflow = true;
+          continue;
+        }
+        const bool front = !part || ikind(r_to_info(sj.w)) == KF;
+        const int at = front ? nf : CAP - 1 - nb;
+        gl[(size_t)at * 64] = (uint16_t)e;
+        nf += front ? 1 : 0;
+        nb += front ? 0 : 1;
       }
       __syncthreads();
     }
-    // the row's entries follow the lane's earlier rows in its flat list
     if (rc > RC || (int)(jhi - jlo) > 4096) overflow = true;
-    const int rcc = rc < RC ? rc : RC;
-    const int mx = wave_max_i(rcc);
-    for (int t = 0; t < mx; ++t)
-      if (t < rcc && cnt + t < CAP) gl[(size_t)(cnt + t) * 64] = rl[t * 64 + lane];
-    cnt += rcc;
   }
-  if (cnt > CAP) overflow = true;
   if (overflow && active) set_err(v.err, ERR_NBCAP);
-  if (!active) cnt = 0;
-  v.nb.cnt[(size_t)w * 64 + lane] = (uint8_t)(cnt < CAP ? cnt : CAP);
+  const int cnt = active ? nf + nb : 0;
+  v.nb.cnt[(size_t)w * 64 + lane] = (uint8_t)cnt;
+  v.nb.split[(size_t)w * 64 + lane] = (uint8_t)(active ? nf : 0);
   unsigned long long pairs = 0;
   if (active) {
     const MatT<R>& M = v.mat[iphase(inf)];
@@ -800,6 +855,17 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
       if (kind == KW) v.p[i] = R(0);
     }
     v.rho[i] = rho;
+    if constexpr (!IsExact<R>::v) {
+      const V4<R> po = v.pos[i];
+      const uint32_t pk = (uint32_t)po.w | (kind << 16) | (iphase(inf) << 18) |
+                          ((v.m[i] != M.mass ? 1u : 0u) << 26);
+      V4<R> pa;
+      pa.x = po.x;
+      pa.y = po.y;
+      pa.z = po.z;
+      pa.w = __uint_as_float(pk);
+      v.pa[i] = pa;
+    }
     V4<R> rm;
     rm.x = rho;
     rm.y = v.m[i];
@@ -831,10 +897,11 @@ __device__ __forceinline__ void extrapolate_wave(const View<R>& v, const Params&
   stage_jlo<DIM>(jl, v.nb, w);
   const WaveGeo g = wave_geo<R>(v, P, wi);
   const V4<R> T = to_frame<R>(v.pos[i], k, g.cx_first, 0, 0);
-  const int n_lane = need ? (int)v.nb.cnt[(size_t)w * 64 + lane] : 0;
+  // fluid neighbours only: the first split entries of a wall / rigid lane
+  const int n_lane = need ? (int)v.nb.split[(size_t)w * 64 + lane] : 0;
   unsigned long long cr = 0, cw = 0;
   const uint32_t c = extrap_one<R, DIM>(v, k, smat, i, need, [&](bool ws, auto&& f) {
-    for_list<R, DIM>(v, k, g, jl, w, n_lane, i, T, ws, f);
+    for_list<R, DIM, true>(v, k, smat, g, jl, w, n_lane, n_lane, i, T, ws, f);
   });
   if (need && kind == KR) cr = c;
   else if (need) cw = c;
@@ -870,9 +937,10 @@ __device__ __forceinline__ void forces_wave(const View<R>& v, const Params& P, c
   stage_jlo<DIM>(jl, v.nb, w);
   const V4<R> T = to_frame<R>(v.pos[i], k, g.cx_first, 0, 0);
   const int n_lane = need ? (int)v.nb.cnt[(size_t)w * 64 + lane] : 0;
+  const int split = v.nb.split[(size_t)w * 64 + lane];
   const double t = (double)(*v.dstep) * P.dt;
   forces_one<R, DIM, THERMAL>(v, P, k, smat, i, need, kick, heat, t, [&](bool ws, auto&& f) {
-    for_list<R, DIM>(v, k, g, jl, w, n_lane, i, T, ws, f);
+    for_list<R, DIM, THERMAL == 0>(v, k, smat, g, jl, w, n_lane, split, i, T, ws, f);
   });
 }
 
@@ -963,9 +1031,9 @@ __global__ void __launch_bounds__(64) k_list_fill(View<R> v, Params P, const uin
   const uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + lane;
   const uint32_t* jlo = v.nb.jlo + (size_t)w * NR;
   uint64_t o = off[v.id[i]];
-  const int c = v.nb.cnt[(size_t)w * 64 + lane];
+  const int c = v.nb.cnt[(size_t)w * 64 + lane], split = v.nb.split[(size_t)w * 64 + lane];
   for (int q = 0; q < c; ++q) {
-    const uint32_t e = gl[(size_t)q * 64];
+    const uint32_t e = gl[(size_t)(q < split ? q : CAP - 1 - (q - split)) * 64];
     const uint32_t j = jlo[e >> 12] + (e & 0xfffu);
     if (j != i) ids[o++] = v.id[j];
   }
@@ -1138,9 +1206,26 @@ __global__ void __launch_bounds__(256) k_fill_u32(uint32_t* p, uint32_t val, int
   if (i < n) p[i] = val;
 }
 
+// Cell counts and a unique rank of every particle inside its cell (the
+// order is fixed later by original id).  The keys arrive nearly sorted (the
+// previous step's order), so each wave adds whole runs of equal keys with
+// one atomic per run.
 __global__ void __launch_bounds__(256) k_count(const uint32_t* key, uint32_t* count, uint32_t* rank, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) rank[i] = atomicAdd(&count[key[i]], 1u);
+  const int lane = threadIdx.x & 63;
+  const bool valid = i < n;
+  const uint32_t k = valid ? key[i] : 0xffffffffu;
+  const uint32_t prev = __shfl_up(k, 1, 64);
+  const bool start = lane == 0 || k != prev;
+  const unsigned long long starts = __ballot(start);
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  const int leader = 63 - __clzll(starts & upto);
+  const unsigned long long after = starts & ~upto;
+  const int next = after ? __ffsll((long long)after) - 1 : 64;
+  uint32_t base = 0u;
+  if (start && valid) base = atomicAdd(&count[k], (uint32_t)(next - lane));
+  base = __shfl(base, leader, 64);
+  if (valid) rank[i] = base + (uint32_t)(lane - leader);
 }
 
 // exclusive scan, 1024 elements per block (256 threads x 4)
@@ -1885,7 +1970,7 @@ __global__ void __launch_bounds__(64) k_ps_nearest(View<R> v, Params P, KC<R> k)
   R br2 = R(0);
   int bb = 0;
   uint32_t bid = 0u;
-  const int c = v.nb.cnt[(size_t)w * 64 + lane];
+  const int c = v.nb.cnt[(size_t)w * 64 + lane];   // a fluid lane: not split
   for (int t = 0; t < c; ++t) {
     const uint32_t e = gl[(size_t)t * 64];
     const int rr = (int)(e >> 12);
@@ -1934,7 +2019,7 @@ __global__ void __launch_bounds__(256) k_ps_components(View<R> v, Params P, cons
       const int lane = (int)(i - v.nb.table[w].p0);
       const uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + lane;
       uint32_t m = v.ps.label[i];
-      const int c = v.nb.cnt[(size_t)w * 64 + lane];
+      const int c = v.nb.cnt[(size_t)w * 64 + lane];   // a fluid lane: not split
       for (int t = 0; t < c; ++t) {
         const uint32_t e = gl[(size_t)t * 64];
         const uint32_t j = v.nb.jlo[(size_t)w * NR + (e >> 12)] + (e & 0xfffu);

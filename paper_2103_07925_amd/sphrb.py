@@ -14,7 +14,8 @@ import re
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsphrb.so")
+# SPHRB_LIB selects another build of the same library (same ABI)
+LIB_PATH = os.environ.get("SPHRB_LIB") or os.path.join(HERE, "libsphrb.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "sphrb.h")
 
 SPH_OK, SPH_E_INVALID, SPH_E_NOMEM, SPH_E_DEVICE, SPH_E_STATE, SPH_E_UNSUPPORTED = range(6)
