@@ -631,52 +631,88 @@ __device__ __forceinline__ int wave_max_i(int x) {
 // density is recovered from its pressure by the inverse equation of state
 // and its mass is that of its phase, unless a flag says otherwise (a phase
 // switch kept the old mass), in which case its full rm record is read.
+// The walk is software-pipelined: while neighbour q is evaluated, the
+// records of q + 1 and the list entry of q + 2 are in flight.
+template <typename R>
+struct NbRec {
+  V4<R> a, vp, rm;
+};
+
 template <typename R, int DIM, bool PACKED, typename F>
 __device__ __forceinline__ void for_list(const View<R>& v, const KC<R>& k, const MatL<R>* sm, const WaveGeo& g,
                                          const uint32_t* jl, int w, int n_lane, int split, uint32_t i,
                                          const V4<R>& T, bool with_self, F&& visit) {
   constexpr int CAP = Nb<DIM>::cap;
+  constexpr bool PK = PACKED && !IsExact<R>::v;
   const uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + threadIdx.x;
   const int nmax = wave_max_i(n_lane);
-  for (int q = 0; q < nmax; ++q) {
-    if (q >= n_lane) continue;
+  // streamed once: kept out of the L1, which holds the gathered records
+  auto entry = [&](int q) -> uint32_t {
     const int at = q < split ? q : CAP - 1 - (q - split);
-    // streamed once: kept out of the L1, which holds the gathered records
-    const uint32_t e = __builtin_nontemporal_load(gl + (size_t)at * 64);
-    const uint32_t rr = e >> 12;
-    const uint32_t j = jl[rr] + (e & 0xfffu);
-    if (j == i && !with_self) continue;
-    const int dz = DIM == 3 ? (int)(rr / 3u) - 1 : 0, dy = (int)(rr % 3u) - 1;
-    Nbr<R> nb;
-    nb.j = j;
-    V4<R> pj;
-    if constexpr (PACKED && !IsExact<R>::v) {
-      const V4<R> a = v.pa[j];
-      const uint32_t pk = __float_as_uint(a.w);
-      pj.x = a.x;
-      pj.y = a.y;
-      pj.z = a.z;
-      pj.w = (R)(pk & 0xffffu);
-      nb.vp = v.vp[j];
-      if ((pk >> 26) & 1u) {
-        nb.rm = v.rm[j];
-      } else {
-        const uint32_t kj = (pk >> 16) & 3u, ph = (pk >> 18) & 0xffu;
-        const MatL<R> M = mat_of<R>(sm, v, ph);
-        nb.rm.x = kj == KF ? inv_eos<R>(M, nb.vp.w) : M.rho0;
-        nb.rm.y = M.mass;
-        nb.rm.z = info_to_r(mkinfo(kj, ph, 0u, -1), R(0));
-        nb.rm.w = R(0);
-      }
+    return __builtin_nontemporal_load(gl + (size_t)at * 64);
+  };
+  auto index = [&](uint32_t e) -> uint32_t { return jl[e >> 12] + (e & 0xfffu); };
+  auto fetch = [&](uint32_t e, NbRec<R>& r) {
+    const uint32_t j = index(e);
+    if constexpr (PK) {
+      r.a = v.pa[j];
+      r.vp = v.vp[j];
     } else {
-      pj = v.pos[j];
-      nb.vp = v.vp[j];
-      nb.rm = v.rm[j];
+      r.a = v.pos[j];
+      r.vp = v.vp[j];
+      r.rm = v.rm[j];
     }
-    const V4<R> sj = to_frame<R>(pj, k, g.cx_first, dy, dz);
-    R d0, d1, d2;
-    const R r2 = dist2<R, DIM>(T, sj, d0, d1, d2);
-    visit(nb, d0, d1, d2, r2);
+  };
+  uint32_t e0 = 0u, e1 = 0u;
+  NbRec<R> r0;
+  if (n_lane > 0) {
+    e0 = entry(0);
+    fetch(e0, r0);
+  }
+  if (n_lane > 1) e1 = entry(1);
+  for (int q = 0; q < nmax; ++q) {
+    NbRec<R> r1;
+    uint32_t e2 = 0u;
+    if (q + 1 < n_lane) fetch(e1, r1);
+    if (q + 2 < n_lane) e2 = entry(q + 2);
+    if (q < n_lane) {
+      const uint32_t rr = e0 >> 12;
+      const uint32_t j = index(e0);
+      if (j != i || with_self) {
+        const int dz = DIM == 3 ? (int)(rr / 3u) - 1 : 0, dy = (int)(rr % 3u) - 1;
+        Nbr<R> nb;
+        nb.j = j;
+        nb.vp = r0.vp;
+        V4<R> pj;
+        if constexpr (PK) {
+          const uint32_t pk = __float_as_uint(r0.a.w);
+          pj.x = r0.a.x;
+          pj.y = r0.a.y;
+          pj.z = r0.a.z;
+          pj.w = (R)(pk & 0xffffu);
+          if ((pk >> 26) & 1u) {
+            nb.rm = v.rm[j];
+          } else {
+            const uint32_t kj = (pk >> 16) & 3u, ph = (pk >> 18) & 0xffu;
+            const MatL<R> M = mat_of<R>(sm, v, ph);
+            nb.rm.x = kj == KF ? inv_eos<R>(M, nb.vp.w) : M.rho0;
+            nb.rm.y = M.mass;
+            nb.rm.z = info_to_r(mkinfo(kj, ph, 0u, -1), R(0));
+            nb.rm.w = R(0);
+          }
+        } else {
+          pj = r0.a;
+          nb.rm = r0.rm;
+        }
+        const V4<R> sj = to_frame<R>(pj, k, g.cx_first, dy, dz);
+        R d0, d1, d2;
+        const R r2 = dist2<R, DIM>(T, sj, d0, d1, d2);
+        visit(nb, d0, d1, d2, r2);
+      }
+    }
+    e0 = e1;
+    e1 = e2;
+    r0 = r1;
   }
 }
 
