@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-side", type=int, default=100)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--other-steps", type=int, default=100,
+                    help="steps of the reduced thermal / moving-wall workloads; 0 skips them")
     ap.add_argument("--serve-scenes", type=int, default=24,
                     help="scenes of the serving run (continuous batching); 0 skips it")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -109,6 +111,41 @@ def serving_run(n_scenes, seed):
                 "capacity_pair_interactions_per_s": cal["pair_interactions_per_s"],
                 "requests": f"{n_scenes} scenes, 1e4-1e5 particles log-uniform, 50 steps each, FP32 sweep"})
     return rep
+
+
+def timed_workload(B, sc, steps, label):
+    """FP32 sweep timing of another workload with the per-stage split."""
+    import torch
+    g = B.SphScene(sc, precision=B.SPH_FP32_SWEEP)
+    g.step(5)
+    g.sync()
+    p0 = g.stats().pairs_total
+    g.sph_scene_enable_timers(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    g.sync()
+    st = g.stats()
+    tm = g.sph_scene_read_timers()
+    nrec = max(tm["steps"], 1)
+    stage = {k: tm[k] / nrec for k in B.SphScene.STAGES}
+    out = {
+        "workload": label, "n_particles": int(sc.n), "counts": sc.counts(), "steps": steps,
+        "ms_per_step": 1e3 * el / steps, "pair_interactions_per_s": (st.pairs_total - p0) / el,
+        "stage_ms_per_step": stage,
+        # the split the moving-wall configuration asks for
+        "split_ms_per_step": {
+            "neighbour_search": stage["integrate"] + stage["neighbor_search"],
+            "interaction_sweep": stage["density"] + stage["extrapolate"] + stage["forces"],
+            "per_body_reduction": stage["body_reduce"] + stage["rigid_velocity"],
+        },
+        "bodies_end": int(st.n_bodies), "melted": int(st.n_melted), "solidified": int(st.n_solidified),
+    }
+    del g
+    torch.cuda.empty_cache()
+    return out
 
 
 def calibrate_copy(mib):
@@ -242,6 +279,17 @@ def main():
                       "fp32_speedup": value / value64},
     }
 
+    if args.other_steps > 0:
+        c3 = S.config_c3(seed=args.seed, nsites=(100, 100, 50), n_grains=250)
+        c4 = S.config_c4(seed=args.seed, nsites=(200, 100, 50), n_frag=62)
+        out["other_workloads"] = [
+            timed_workload(B, c3, args.other_steps,
+                           "two-phase thermal grains with conduction, moving heat source and phase switching, "
+                           "1/8 of the 200x200x100-site box (100x100x50 sites, 250 grains requested)"),
+            timed_workload(B, c4, args.other_steps,
+                           "container with a moving perforated wall plate and 2-6-sphere fragments in contact, "
+                           "1/8 of the 400x200x100-site box (200x100x50 sites, 62 fragments)"),
+        ]
     if args.serve_scenes > 0:
         out["serving"] = serving_run(args.serve_scenes, args.seed)
         torch.cuda.empty_cache()

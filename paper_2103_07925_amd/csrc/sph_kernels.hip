@@ -608,12 +608,14 @@ __device__ __forceinline__ R dist2(const V4<R>& T, const V4<R>& s, R& d0, R& d1,
   return r2;
 }
 
+// maximum over the wave, returned as a wave-uniform (scalar) value so that
+// loops bounded by it are controlled by scalar instructions
 __device__ __forceinline__ int wave_max_i(int x) {
   for (int off = 32; off > 0; off >>= 1) {
     int y = __shfl_xor(x, off, 64);
     x = y > x ? y : x;
   }
-  return x;
+  return __builtin_amdgcn_readfirstlane(x);
 }
 
 // Walk one lane's list: entry q of lane l sits at [wave][q][l] (entries
@@ -843,26 +845,27 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
         e += 4u;
       }
       // density of this segment's hits, and the hits into the lane's list
+      // (predicated rather than branched: lanes past their hits add zero)
       const int t1 = rc < RC ? rc : RC;
       const int mh = wave_max_i(t1 - rc0);
-      for (int t = rc0; t < rc0 + mh; ++t) {
-        if (t >= t1) continue;
-        const uint32_t e = rl[t * 64 + lane];
-        const V4<R> sj = stg[(int)(e & 0xfffu) - (int)so];
-        if (dens) {
-          R d0, d1, d2;
-          const R r2 = dist2<R, DIM>(T, sj, d0, d1, d2);
-          sum = sum + kern_w<R>(ksqrt(r2), k);
-        }
-        if (nf + nb >= CAP) {
-          overflow = true;
-          continue;
-        }
+      for (int u = 0; u < mh; ++u) {     // uniform trip count
+        const int t = rc0 + u;
+        const bool valid = t < t1;
+        const uint32_t e = rl[(valid ? t : rc0) * 64 + lane];
+        const int qq = (int)(e & 0xfffu) - (int)so;
+        const V4<R> sj = stg[valid ? qq : 0];
+        R d0, d1, d2;
+        const R r2 = dist2<R, DIM>(T, sj, d0, d1, d2);
+        const R wv = kern_w<R>(ksqrt(r2), k);
+        if (valid && dens) sum = sum + wv;
+        const bool room = nf + nb < CAP;
+        overflow = overflow || (valid && !room);
         const bool front = !part || ikind(r_to_info(sj.w)) == KF;
         const int at = front ? nf : CAP - 1 - nb;
-        gl[(size_t)at * 64] = (uint16_t)e;
-        nf += front ? 1 : 0;
-        nb += front ? 0 : 1;
+        const bool put = valid && room;
+        if (put) gl[(size_t)at * 64] = (uint16_t)e;
+        nf += (put && front) ? 1 : 0;
+        nb += (put && !front) ? 1 : 0;
       }
       __syncthreads();
     }
