@@ -277,7 +277,7 @@ void carve(Carver& cv, sph_scene* s, const Params& P, int64_t nmat) {
   s->err = cv.take<uint32_t>(4);
   s->pairs = cv.take<unsigned long long>(6);
   // compact neighbour lists: one slot per possible wave
-  const int cap = P.dim == 3 ? 192 : 64, nsr = P.dim == 3 ? 9 : 3;
+  const int cap = 192, nsr = P.dim == 3 ? 9 : 3;
   s->nb.table = cv.take<WaveInfo>((size_t)P.max_waves);
   s->nb.ent = cv.take<uint16_t>((size_t)P.max_waves * cap * 64);
   s->nb.cnt = cv.take<uint8_t>((size_t)P.max_waves * 64);

@@ -545,7 +545,7 @@ __device__ __forceinline__ void forces_one(const View<R>& v, const Params& P, co
 // ---------------------------------------------------------------------------
 
 template <int DIM> struct Nb {
-  static constexpr int cap = DIM == 3 ? 192 : 64;   // entries per lane (self included)
+  static constexpr int cap = 192;   // entries per lane, self included (counts are bytes)
   static constexpr int rows = DIM == 3 ? 9 : 3;
 };
 template <typename R> struct Win { static constexpr int v = 256; };
@@ -759,13 +759,12 @@ __global__ void __launch_bounds__(256) k_row_waves_fill(const uint32_t* cstart, 
 // force sweeps.  The equation of state (eq. nummeth_fluid_eos) closes the
 // density; the packed neighbour records rm (all particles) and vp (fluid)
 // are written here.
-template <int DIM> struct RowCap { static constexpr int v = DIM == 3 ? 64 : 32; };
 
 template <typename R, int DIM>
 __device__ __forceinline__ void build_density_wave(const View<R>& v, const Params& P, const KC<R>& k, int w) {
-  constexpr int CAP = Nb<DIM>::cap, NR = Nb<DIM>::rows, WIN = Win<R>::v, RC = RowCap<DIM>::v;
-  __shared__ V4<R> stg[WIN + 4];
-  __shared__ uint16_t rl[RC * 64];
+  constexpr int CAP = Nb<DIM>::cap, NR = Nb<DIM>::rows, WIN = Win<R>::v, NWD = WIN / 32;
+  __shared__ V4<R> stg[WIN + 32];
+  __shared__ uint32_t msk[NWD * 64];
   if (w >= (int)*v.nb.nwaves) return;
   const WaveInfo wi = v.nb.table[w];
   const int lane = threadIdx.x;
@@ -803,10 +802,9 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
     }
     if (!active) lhi = llo;
     if (lane == rr) v.nb.jlo[(size_t)w * NR + rr] = jlo;
-    int rc = 0;
     for (uint32_t seg = jlo; seg < jhi; seg += (uint32_t)WIN) {
       const int ns = (int)(jhi - seg < (uint32_t)WIN ? jhi - seg : (uint32_t)WIN);
-      for (int q = lane; q < ns + 4; q += 64) {
+      for (int q = lane; q < ns + 32; q += 64) {
         V4<R> sq;
         if (q < ns) {
           sq = to_frame<R>(v.pos[seg + q], k, g.cx_first, dy, dz);
@@ -818,7 +816,6 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
         stg[q] = sq;
       }
       __syncthreads();
-      const int rc0 = rc;
       const uint32_t so = seg - jlo;
       const uint32_t tag = ((uint32_t)rr << 12) | so;
       // this lane's candidates inside the segment: [qa, qb); every lane
@@ -828,48 +825,49 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
       const int qa = (int)((llo > so ? llo : so) - so);
       int qb = (int)((lhi < so + (uint32_t)ns ? lhi : so + (uint32_t)ns) - so);
       if (qb < qa) qb = qa;
-      if (jhi - jlo > 4096u) qb = qa;     // entries hold 12-bit offsets: an error, below
+      if (jhi - jlo > 4096u) {            // entries hold 12-bit offsets: an error
+        qb = qa;
+        overflow = overflow || active;
+      }
       const int mlen = wave_max_i(qb - qa);
       const int qs = qa < ns - mlen ? qa : ns - mlen;
-      const V4<R>* sp = stg + qs;
-      uint32_t e = tag + (uint32_t)qs;
-      for (int t = 0; t < mlen; t += 4) {
-        R e0, e1, e2;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const R a0 = dist2<R, DIM>(V4<R>{T0, T1, T2, R(0)}, sp[t + u], e0, e1, e2);
-          const int slot = rc < RC ? rc : RC - 1;
-          rl[slot * 64 + lane] = (uint16_t)(e + (uint32_t)u);
-          rc += a0 < k.rc2 ? 1 : 0;
+      const int nwd = (mlen + 31) >> 5;
+      // candidate tests: bit 31 - u of word wd is candidate qs + 32 wd + u
+      for (int wd = 0; wd < nwd; ++wd) {
+        const V4<R>* sp = stg + qs + 32 * wd;
+        uint32_t m = 0u;
+#pragma unroll 8
+        for (int u = 0; u < 32; ++u) {
+          R e0, e1, e2;
+          const R a0 = dist2<R, DIM>(V4<R>{T0, T1, T2, R(0)}, sp[u], e0, e1, e2);
+          m = m + m + (a0 < k.rc2 ? 1u : 0u);
         }
-        e += 4u;
+        msk[wd * 64 + lane] = m;
       }
-      // density of this segment's hits, and the hits into the lane's list
-      // (predicated rather than branched: lanes past their hits add zero)
-      const int t1 = rc < RC ? rc : RC;
-      const int mh = wave_max_i(t1 - rc0);
-      for (int u = 0; u < mh; ++u) {     // uniform trip count
-        const int t = rc0 + u;
-        const bool valid = t < t1;
-        const uint32_t e = rl[(valid ? t : rc0) * 64 + lane];
-        const int qq = (int)(e & 0xfffu) - (int)so;
-        const V4<R> sj = stg[valid ? qq : 0];
-        R d0, d1, d2;
-        const R r2 = dist2<R, DIM>(T, sj, d0, d1, d2);
-        const R wv = kern_w<R>(ksqrt(r2), k);
-        if (valid && dens) sum = sum + wv;
-        const bool room = nf + nb < CAP;
-        overflow = overflow || (valid && !room);
-        const bool front = !part || ikind(r_to_info(sj.w)) == KF;
-        const int at = front ? nf : CAP - 1 - nb;
-        const bool put = valid && room;
-        if (put) gl[(size_t)at * 64] = (uint16_t)e;
-        nf += (put && front) ? 1 : 0;
-        nb += (put && !front) ? 1 : 0;
+      // the hits in candidate order: density, and into the lane's list
+      for (int wd = 0; wd < nwd; ++wd) {
+        uint32_t m = msk[wd * 64 + lane];
+        while (m != 0u) {
+          const int bit = __builtin_clz(m);
+          m &= ~(0x80000000u >> bit);
+          const int q = qs + 32 * wd + bit;
+          const V4<R> sj = stg[q];
+          if (dens) {
+            R d0, d1, d2;
+            const R r2 = dist2<R, DIM>(T, sj, d0, d1, d2);
+            sum = sum + kern_w<R>(ksqrt(r2), k);
+          }
+          const bool room = nf + nb < CAP;
+          overflow = overflow || !room;
+          const bool front = !part || ikind(r_to_info(sj.w)) == KF;
+          const int at = front ? nf : CAP - 1 - nb;
+          if (room) gl[(size_t)at * 64] = (uint16_t)(tag + (uint32_t)q);
+          nf += (room && front) ? 1 : 0;
+          nb += (room && !front) ? 1 : 0;
+        }
       }
       __syncthreads();
     }
-    if (rc > RC || (int)(jhi - jlo) > 4096) overflow = true;
   }
   if (overflow && active) set_err(v.err, ERR_NBCAP);
   const int cnt = active ? nf + nb : 0;
@@ -1117,12 +1115,21 @@ __global__ void __launch_bounds__(256) k_kick_drift(View<R> v, Params P, KC<R> k
       bool esc = false;
       for (int a = 0; a < P.dim; ++a) {
         o[a] = kfma(k.dt, uu[a], o[a]);
-        if (o[a] >= k.L) { o[a] -= k.L; c3[a] += 1; }
-        else if (o[a] < R(0)) { o[a] += k.L; c3[a] -= 1; }
+        if (o[a] >= k.L || o[a] < R(0)) {
+          // re-home by as many cells as the particle moved (one at most
+          // under the time-step bounds; more only after a blow-up)
+          const R sh = floorf(o[a] / k.L);
+          if (!(fabsf(sh) < R(1 << 24))) {
+            esc = true;
+          } else {
+            const int ish = (int)sh;
+            o[a] = o[a] - sh * k.L;
+            if (ish < -c3[a] || ish > P.nc[a] - 1 - c3[a]) esc = true;
+            else c3[a] += ish;
+          }
+        }
         if (o[a] < R(0)) o[a] = R(0);
         if (o[a] > k.L) o[a] = k.L;
-        if (c3[a] < 0) { c3[a] = 0; esc = true; }
-        if (c3[a] >= P.nc[a]) { c3[a] = P.nc[a] - 1; esc = true; }
       }
       if (esc || !isfinite(o[0]) || !isfinite(o[1]) || !isfinite(o[2])) set_err(v.err, esc ? ERR_ESCAPE : ERR_NONFINITE);
       x.x = o[0]; x.y = o[1]; x.z = o[2]; x.w = (R)c3[0];

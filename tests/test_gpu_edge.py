@@ -1,0 +1,137 @@
+"""GPU edge cases through the C ABI: empty and one-particle scenes, ragged
+clustered clouds, bodies without fluid, the error paths of the sticky
+device error word, FP32 with heat and phase switching, and the full-size
+3D column workload (the configuration the benchmark times) against the
+oracle after two steps."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2103_07925_amd import scenes as S
+
+from parity_util import body_errors, field_errors, gpu_fields, oracle_fields, run_pair
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2103_07925_amd import sphrb
+    sphrb.lib()
+    return sphrb
+
+
+def _subset(sc, keep):
+    """The scene restricted to the particles in `keep` (no bodies)."""
+    out = dataclasses.replace(sc)
+    for f in ("x", "u", "T", "kind", "phase", "body", "moving"):
+        setattr(out, f, np.ascontiguousarray(getattr(sc, f)[keep]))
+    out.bodies = []
+    return out
+
+
+def test_empty_scene(B):
+    sc = _subset(S.fluid_box(dim=3, n_side=6), np.zeros(0, dtype=np.int64))
+    for prec in (B.SPH_FP64, B.SPH_FP32_SWEEP):
+        g = B.SphScene(sc, precision=prec, dt=1e-4)
+        g.step(3)
+        g.sync()
+        st = g.stats()
+        assert st.n == 0 and st.pairs_total == 0 and st.mass == 0.0
+        assert g.bodies().shape == (0, B.SPH_BODY_REC)
+
+
+def test_single_particle(B):
+    sc = _subset(S.fluid_box(dim=3, n_side=6, g=9.81), np.array([100]))
+    o, g = run_pair(sc, B.SPH_FP64, 5, dt=1e-4)
+    e = field_errors(sc, gpu_fields(g), oracle_fields(o), sc.kind)
+    assert max(e.values()) <= FP64_TOL, e
+    assert g.stats().pairs_last == 0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_clustered_cloud_fp64_parity(B, dim):
+    """Dense clusters and empty cells: ragged waves and rows, long windows."""
+    sc = S.random_cloud(dim, 3000 if dim == 3 else 1500, extent=2.0, dx=0.05, seed=7, clustered=True)
+    o, g = run_pair(sc, B.SPH_FP64, 3, dt=1e-5)
+    off_o, ids_o = o.neighbors()
+    off_g, ids_g = g.neighbors()
+    assert np.array_equal(off_o, off_g) and np.array_equal(ids_o, ids_g)
+    e = field_errors(sc, gpu_fields(g), oracle_fields(o), sc.kind)
+    assert max(e.values()) <= FP64_TOL, e
+
+
+def test_bodies_without_fluid(B):
+    """A spinning, falling body alone: no fluid neighbours, no extrapolation
+    sources; the body follows free fall and torque-free spin."""
+    sc = S.single_body(3, radius_sites=3.0, w0=(0.4, -0.3, 1.1), u0=(0.2, 0.0, 0.1))
+    o, g = run_pair(sc, B.SPH_FP64, 40, dt=1e-3)
+    eb = body_errors(sc, g.bodies(), o.bodies())
+    assert max(eb.values()) <= FP64_TOL, eb
+
+
+def test_escape_is_a_sticky_error(B):
+    """A particle driven out of the cell grid sets the escape bit; the step
+    finishes normally and sync reports the error."""
+    sc = S.fluid_box(dim=2, n_side=8, walls=False)
+    sc.u[0] = (1e4, 0.0, 0.0)
+    g = B.SphScene(sc, precision=B.SPH_FP32_SWEEP, dt=1e-3)
+    g.step(2)
+    with pytest.raises(RuntimeError):
+        g.sync()
+    assert g.stats().device_error & 1
+
+
+def test_fp32_thermal_switching_gates(B):
+    """FP32 sweep with conduction and phase switching (temperatures kept away
+    from T_t, so the switching decisions are the oracle's)."""
+    from test_gpu_parity import _scripted_switch_scene
+    sc = _scripted_switch_scene()
+    rigid = np.nonzero(sc.kind == S.RIGID)[0]
+    sc.T[rigid[-1]] = 40.0
+    sc.T[rigid[5]] = 40.0
+    sc.materials[0].kappa = 0.5
+    sc.materials[2].kappa = 0.5
+    o, g = run_pair(sc, B.SPH_FP32_SWEEP, 1)
+    kind = o.get_int(O.I_KIND)
+    assert np.array_equal(g.flags()[0], kind)
+    assert g.bodies().shape == o.bodies().shape
+    e = field_errors(sc, gpu_fields(g), oracle_fields(o), kind)
+    for key in ("x", "u", "rho", "p", "T"):
+        assert e[key] <= 1e-5, (key, e)
+    eb = body_errors(sc, g.bodies(), o.bodies())
+    assert eb["r"] <= 1e-5 and eb["m"] <= 1e-12, eb
+
+
+def test_full_size_column_two_steps(B):
+    """The benchmark's 1,191,016-particle column: FP64 pair count, cell order
+    and fields against the oracle after two steps; FP32 within its one-step
+    gates (checked after two)."""
+    sc = S.config_c2(seed=0)
+    o = O.OracleScene(sc)
+    o.step(2)
+    of = oracle_fields(o)
+    g = B.SphScene(sc, precision=B.SPH_FP64)
+    g.step(2)
+    g.sync()
+    assert g.stats().pairs_last == o.pair_count
+    so, co = o.cell_order()
+    sg, cg = g.cell_order()
+    assert np.array_equal(so, sg) and np.array_equal(co, cg)
+    e = field_errors(sc, gpu_fields(g), of, sc.kind)
+    assert max(e.values()) <= FP64_TOL, e
+    assert max(body_errors(sc, g.bodies(), o.bodies()).values()) <= FP64_TOL
+    del g
+    g32 = B.SphScene(sc, precision=B.SPH_FP32_SWEEP)
+    g32.step(2)
+    g32.sync()
+    e32 = field_errors(sc, gpu_fields(g32), of, sc.kind)
+    for key in ("x", "u", "rho", "p", "pw", "uw"):
+        assert e32[key] <= 1e-5, (key, e32)
