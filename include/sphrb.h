@@ -171,7 +171,13 @@ int sph_scene_step(sph_scene *s, int64_t nsteps);
  *     only one may step it at a time.
  *   sph_batch_step: enqueues nsteps steps of every scene; asynchronous.
  *     Work already enqueued on a scene's own stream is waited for, and the
- *     scene's stream waits for the batch's work, through events.
+ *     scene's stream waits for the batch's work, through events.  Once the
+ *     batch has taken a step in a given state of the scenes' buffer
+ *     parities (there are two, alternating), the next step in that state is
+ *     captured as a HIP graph and later ones replay it (not on the null
+ *     stream; environment variable SPHRB_BATCH_GRAPHS=0 at
+ *     sph_batch_create turns this off).
+ *     Per-step timers of the scenes do not record batch steps.
  *   sph_batch_destroy: waits for the batch stream and frees the host side. */
 typedef struct sph_batch sph_batch;
 size_t sph_batch_bytes(int32_t n);

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -131,6 +132,16 @@ struct sph_batch {
   char* ws;
   size_t ws_bytes;
   std::vector<hipEvent_t> ev;        // one per scene, plus one for the batch stream
+  // One step of all scenes captured as a HIP graph, for each of the (at
+  // most two) buffer-parity states the scenes go through; a later step in
+  // the same state replays it.  Every launch argument of a step is fixed
+  // by the parities (times come from the scenes' device step counters).
+  struct Graph {
+    std::vector<int> key;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> graphs;
+  int use_graphs;
 };
 
 namespace {
@@ -500,8 +511,7 @@ void pre_step(sph_scene* s, hipEvent_t* ev) {
   const KC<R> k = make_kc<R>(P);
   const double t_new = (double)(s->step + 1) * P.dt;
   if (ev) (void)hipEventRecord(ev[0], s->stream);
-  launch_step_begin(s->pairs, s->dstep, s->stream);
-  View<R> v = cur<R>(s);
+  View<R> v = cur<R>(s);   // kick_drift also starts the step (counters)
   Launch<R>::kick_drift(v, P, k, s->sb, s->stream);
   launch_body_kick_drift(s->bodies, P, P.pswitch ? s->dyn + 1 : nullptr, s->stream);
   Launch<R>::rigid_pose(v, P, k, s->sb, t_new, s->stream);
@@ -576,8 +586,13 @@ int group_table(sph_batch* b, sph_batch::Group& g, int* which_out) {
     }
   const int which = g.key[0].empty() ? 0 : 1;
   *which_out = which;
-  // a table in flight is replaced: wait for the batch stream first
-  if (!g.key[which].empty()) HIP_TRY(hipStreamSynchronize(b->stream));
+  // a table in flight is replaced: wait for the batch stream first; graphs
+  // captured with the old table are dropped
+  if (!g.key[which].empty()) {
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (auto& gr : b->graphs) (void)hipGraphExecDestroy(gr.exec);
+    b->graphs.clear();
+  }
   const size_t sb = slot_bytes(g.precision);
   g.host[which].assign(g.members.size() * sb, 0);
   uint32_t b0 = 0;
@@ -599,6 +614,88 @@ template <typename R>
 void group_sweep(sph_batch* b, sph_batch::Group& g, int which, int stage) {
   Launch<R>::batch_sweep(stage, reinterpret_cast<const Slot<R>*>(b->ws + g.off[which]), (int)g.members.size(),
                          g.dim, g.thermal, g.blocks, 1, 1, b->stream);
+}
+
+// the host-side bookkeeping of one step, without its launches (a replayed
+// graph did the device work): the buffer parities and the step count change
+// exactly as pre_step / after_sweeps / post_step change them
+void advance_host_state(sph_scene* s) {
+  s->ip = 1 - s->ip;
+  s->iT = 1 - s->iT;
+  if (s->P.thermal) s->iT = 1 - s->iT;
+  s->step += 1;
+}
+
+std::vector<int> parity_key(const sph_batch* b) {
+  std::vector<int> key;
+  for (const sph_scene* s : b->scenes) key.push_back(s->ip * 4 + s->iu * 2 + s->iT);
+  return key;
+}
+
+// enqueue one step of every scene of the batch (no graph)
+int batch_enqueue_step(sph_batch* b) {
+  for (sph_scene* s : b->scenes) {
+    if (s->precision == SPH_FP64) pre_step<double>(s, nullptr);
+    else pre_step<float>(s, nullptr);
+  }
+  std::vector<int> which(b->groups.size());
+  for (size_t g = 0; g < b->groups.size(); ++g)
+    if (int st = group_table(b, b->groups[g], &which[g])) return st;
+  for (int stage = 0; stage < 3; ++stage)
+    for (size_t g = 0; g < b->groups.size(); ++g) {
+      sph_batch::Group& G = b->groups[g];
+      if (G.precision == SPH_FP64) group_sweep<double>(b, G, which[g], stage);
+      else group_sweep<float>(b, G, which[g], stage);
+    }
+  for (sph_scene* s : b->scenes) {
+    if (s->precision == SPH_FP64) post_step<double>(s, nullptr);
+    else post_step<float>(s, nullptr);
+  }
+  return SPH_OK;
+}
+
+// the slot tables of the state after the sort of the coming step exist
+bool tables_ready(sph_batch* b) {
+  for (auto& g : b->groups) {
+    std::vector<int> key;
+    for (int m : g.members) {
+      const sph_scene* s = b->scenes[m];
+      // the sweeps see the parities after the sort: ip, iu and iT flipped
+      key.push_back((1 - s->ip) * 4 + (1 - s->iu) * 2 + (1 - s->iT));
+    }
+    if (key != g.key[0] && key != g.key[1]) return false;
+  }
+  return true;
+}
+
+int batch_one_step(sph_batch* b) {
+  if (!b->use_graphs) return batch_enqueue_step(b);
+  const std::vector<int> key = parity_key(b);
+  for (auto& g : b->graphs)
+    if (g.key == key) {
+      HIP_TRY(hipGraphLaunch(g.exec, b->stream));
+      for (sph_scene* s : b->scenes) advance_host_state(s);
+      return SPH_OK;
+    }
+  // not captured yet: a plain step while a slot table is still missing,
+  // else capture this step (the capture advances the host state) and run it
+  if (b->graphs.size() >= 2 || !tables_ready(b)) return batch_enqueue_step(b);
+  HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
+  const int st = batch_enqueue_step(b);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->stream, &graph);
+  if (st != SPH_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return fail(SPH_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e2 != hipSuccess) return fail(SPH_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+  b->graphs.push_back({key, exec});
+  HIP_TRY(hipGraphLaunch(exec, b->stream));
+  return SPH_OK;
 }
 
 template <typename R>
@@ -786,6 +883,7 @@ int create_impl(const sph_scene_desc* d, sph_scene* s) {
   if (P.pswitch) launch_fill_u32(s->ps.dirty, 0u, std::max(P.maxb, 1), st);
   zero_pairs(s, true);
   launch_fill_u32(reinterpret_cast<uint32_t*>(s->dstep), 0u, 2, st);
+  launch_fill_u32(s->sb.ccount, 0u, P.ncells, st);
   s->ip = 0;
   s->iu = 0;
   s->iT = 0;
@@ -1106,6 +1204,12 @@ int sph_batch_create(sph_scene* const* scenes, int32_t n, void* dev_ws, size_t w
   if (!b) return fail(SPH_E_NOMEM, "host allocation");
   b->scenes.assign(scenes, scenes + n);
   b->stream = (hipStream_t)hip_stream;
+  {
+    const char* gv = std::getenv("SPHRB_BATCH_GRAPHS");
+    b->use_graphs = gv ? (std::atoi(gv) != 0) : 1;
+    // the null stream cannot be captured
+    if (!b->stream) b->use_graphs = 0;
+  }
   b->ws = (char*)dev_ws;
   b->ws_bytes = ws_bytes;
   size_t off = 0;
@@ -1159,25 +1263,7 @@ int sph_batch_step(sph_batch* b, int64_t nsteps) {
     s->stream = b->stream;
   }
   int st = SPH_OK;
-  for (int64_t k = 0; k < nsteps && st == SPH_OK; ++k) {
-    for (sph_scene* s : b->scenes) {
-      if (s->precision == SPH_FP64) pre_step<double>(s, nullptr);
-      else pre_step<float>(s, nullptr);
-    }
-    std::vector<int> which(b->groups.size());
-    for (size_t g = 0; g < b->groups.size() && st == SPH_OK; ++g) st = group_table(b, b->groups[g], &which[g]);
-    if (st != SPH_OK) break;
-    for (int stage = 0; stage < 3; ++stage)
-      for (size_t g = 0; g < b->groups.size(); ++g) {
-        sph_batch::Group& G = b->groups[g];
-        if (G.precision == SPH_FP64) group_sweep<double>(b, G, which[g], stage);
-        else group_sweep<float>(b, G, which[g], stage);
-      }
-    for (sph_scene* s : b->scenes) {
-      if (s->precision == SPH_FP64) post_step<double>(s, nullptr);
-      else post_step<float>(s, nullptr);
-    }
-  }
+  for (int64_t k = 0; k < nsteps && st == SPH_OK; ++k) st = batch_one_step(b);
   for (size_t q = 0; q < n; ++q) b->scenes[q]->stream = own[q];
   if (other) {
     HIP_TRY(hipEventRecord(b->ev[n], b->stream));
@@ -1193,6 +1279,7 @@ int sph_batch_step(sph_batch* b, int64_t nsteps) {
 void sph_batch_destroy(sph_batch* b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->stream);
+  for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.exec);
   for (auto& e : b->ev)
     if (e) (void)hipEventDestroy(e);
   delete b;

@@ -1081,9 +1081,17 @@ __global__ void __launch_bounds__(64) k_list_fill(View<R> v, Params P, const uin
 // ---------------------------------------------------------------------------
 
 // first kick and drift of fluid particles, new cell keys of every particle
+// (the first thread also starts the step: pair counters, step counter)
 template <typename R>
 __global__ void __launch_bounds__(256) k_kick_drift(View<R> v, Params P, KC<R> k, uint32_t* key) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    v.pairs[0] = 0ull;
+    v.pairs[2] = 0ull;
+    v.pairs[3] = 0ull;
+    v.pairs[4] = 0ull;
+    v.dstep[0] = v.dstep[0] + 1ull;
+  }
   if (i >= P.n) return;
   const uint32_t inf = v.info[i];
   uint32_t c = v.cell[i];
@@ -1180,11 +1188,13 @@ __global__ void __launch_bounds__(256) k_rigid_pose(View<R> v, Params P, uint32_
   v.s_aw[s] = aw;
 }
 
-// moving boundary particles: displacement A (cos(Omega t) - 1) along dir
+// moving boundary particles: displacement A (cos(Omega t) - 1) along dir, at
+// t = (steps begun) x dt from the scene's device step counter
 template <typename R>
-__global__ void __launch_bounds__(256) k_wall_motion(View<R> v, Params P, uint32_t* key, double t) {
+__global__ void __launch_bounds__(256) k_wall_motion(View<R> v, Params P, uint32_t* key) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= P.n_moving) return;
+  const double t = (double)(*v.dstep) * P.dt;
   const int64_t i = v.w_sorted[s];
   const double sA = P.wall_A * (cos(P.wall_Om * t) - 1.0);
   const double vA = -P.wall_A * P.wall_Om * sin(P.wall_Om * t);
@@ -1735,6 +1745,91 @@ __global__ void __launch_bounds__(256) k_global_final(const double* part, int nb
 }
 
 // ---------------------------------------------------------------------------
+// single-workgroup forms of the scan and the wave table for small arrays:
+// one launch instead of three
+// ---------------------------------------------------------------------------
+
+constexpr int64_t kSmallScan = 16384;     // scans: one workgroup up to here
+constexpr int64_t kSmallRows = 65536;     // wave table: one workgroup up to here
+
+// exclusive scan over the 1024 threads of the workgroup
+__device__ __forceinline__ uint32_t block1024_exclusive_scan(uint32_t x, uint32_t* total) {
+  __shared__ uint32_t wsum[16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t inc = x;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += y;
+  }
+  if (lane == 63) wsum[wid] = inc;
+  __syncthreads();
+  uint32_t base = 0u, tot = 0u;
+  for (int w = 0; w < 16; ++w) {
+    const uint32_t v = wsum[w];
+    if (w < wid) base += v;
+    tot += v;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + inc - x;
+}
+
+// out[i] = sum of in[0..i), out[n] = total; in is cleared when asked (the
+// cell counts, ready for the next step).  Tiles of 4096 entries, each
+// thread four consecutive ones, a running carry between tiles.
+__global__ void __launch_bounds__(1024) k_scan_small(uint32_t* in, uint32_t* out, int64_t n, int clear,
+                                                     const uint32_t* gate) {
+  if (gate && gate[0] == 0u) return;
+  uint32_t carry = 0u;
+  for (int64_t base = 0; base < n; base += 4096) {
+    const int64_t a = base + 4 * (int64_t)threadIdx.x;
+    uint32_t v[4], sum = 0u;
+    for (int q = 0; q < 4; ++q) {
+      v[q] = a + q < n ? in[a + q] : 0u;
+      sum += v[q];
+    }
+    uint32_t tot;
+    uint32_t run = carry + block1024_exclusive_scan(sum, &tot);
+    for (int q = 0; q < 4; ++q)
+      if (a + q < n) {
+        out[a + q] = run;
+        run += v[q];
+        if (clear) in[a + q] = 0u;
+      }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) out[n] = carry;
+}
+
+// waves of every x-row of cells (64 particles at most, one row each) and
+// the wave table, in one workgroup; woff[nrows] receives the wave count
+__global__ void __launch_bounds__(1024) k_wave_table_small(const uint32_t* cstart, int nx, int64_t nrows,
+                                                           uint32_t* woff, WaveInfo* table) {
+  const int64_t chunk = (nrows + 1023) / 1024;
+  const int64_t a = (int64_t)threadIdx.x * chunk;
+  const int64_t b = a + chunk < nrows ? a + chunk : nrows;
+  uint32_t sum = 0u;
+  for (int64_t r = a; r < b; ++r) sum += (cstart[(r + 1) * nx] - cstart[r * nx] + 63u) >> 6;
+  uint32_t tot;
+  uint32_t w0 = block1024_exclusive_scan(sum, &tot);
+  for (int64_t r = a; r < b; ++r) {
+    const uint32_t s0 = cstart[r * nx];
+    const uint32_t n = cstart[(r + 1) * nx] - s0;
+    woff[r] = w0;
+    for (uint32_t q = 0; q * 64u < n; ++q) {
+      WaveInfo wi;
+      wi.p0 = s0 + 64u * q;
+      wi.cnt = n - 64u * q < 64u ? n - 64u * q : 64u;
+      wi.row = (uint32_t)r;
+      wi.pad = 0u;
+      table[w0 + q] = wi;
+    }
+    w0 += (n + 63u) >> 6;
+  }
+  if (threadIdx.x == 0) woff[nrows] = tot;
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 
@@ -1750,6 +1845,10 @@ void launch_step_begin(unsigned long long* pairs, unsigned long long* dstep, hip
 
 void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum, hipStream_t st,
                      const uint32_t* gate) {
+  if (n <= kSmallScan) {
+    k_scan_small<<<1, 1024, 0, st>>>(const_cast<uint32_t*>(in), out, n, 0, gate);
+    return;
+  }
   const int64_t nb = (n + 1023) / 1024;
   if (nb > 0) k_scan_blocks<<<(unsigned)nb, 256, 0, st>>>(in, out, bsum, n, gate);
   k_scan_bsum<<<1, 256, 0, st>>>(bsum, nb, out + n, gate);
@@ -1758,16 +1857,24 @@ void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsu
 
 void launch_wave_table(const Params& P, const uint32_t* cstart, uint32_t* wcount, uint32_t* woff, uint32_t* bsum,
                        WaveInfo* table, hipStream_t st) {
+  if (P.nrows <= kSmallRows) {
+    k_wave_table_small<<<1, 1024, 0, st>>>(cstart, P.nc[0], P.nrows, woff, table);
+    return;
+  }
   k_row_waves<<<nblk(P.nrows), 256, 0, st>>>(cstart, P.nc[0], P.nrows, wcount);
   launch_scan_u32(wcount, woff, P.nrows, bsum, st);
   k_row_waves_fill<<<nblk(P.nrows), 256, 0, st>>>(cstart, P.nc[0], P.nrows, woff, table);
 }
 
+// the cell counts are zero on entry: cleared at creation and by the
+// single-workgroup scan after use (the multi-workgroup path clears them here)
 void launch_sort_keys(const Params& P, SortBufs sb, uint32_t* cstart, const uint32_t* id, hipStream_t st) {
   const int64_t C = P.ncells, n = P.n;
-  launch_fill_u32(sb.ccount, 0u, C, st);
+  const bool small = C <= kSmallScan;
+  if (!small) launch_fill_u32(sb.ccount, 0u, C, st);
   if (n > 0) k_count<<<nblk(n), 256, 0, st>>>(sb.key, sb.ccount, sb.rank, n);
-  launch_scan_u32(sb.ccount, cstart, C, sb.bsum, st);
+  if (small) k_scan_small<<<1, 1024, 0, st>>>(sb.ccount, cstart, C, 1, nullptr);
+  else launch_scan_u32(sb.ccount, cstart, C, sb.bsum, st);
   if (n > 0) {
     k_scatter<<<nblk(n), 256, 0, st>>>(sb.key, sb.rank, cstart, id, sb.tid, sb.tsrc, n);
   }
@@ -1802,14 +1909,15 @@ void launch_rigid_aw(Body* b, const Params& P, const int32_t* s_body, const V4<d
 template <typename R>
 void Launch<R>::kick_drift(const View<R>& v, const Params& P, const KC<R>& k, SortBufs sb, hipStream_t st) {
   if (P.n > 0) k_kick_drift<R><<<nblk(P.n), 256, 0, st>>>(v, P, k, sb.key);
+  else launch_step_begin(v.pairs, v.dstep, st);
 }
 template <typename R>
 void Launch<R>::rigid_pose(const View<R>& v, const Params& P, const KC<R>&, SortBufs sb, double, hipStream_t st) {
   if (P.slot_cap > 0) k_rigid_pose<R><<<nblk(P.slot_cap), 256, 0, st>>>(v, P, sb.key);
 }
 template <typename R>
-void Launch<R>::wall_motion(const View<R>& v, const Params& P, const KC<R>&, SortBufs sb, double t, hipStream_t st) {
-  if (P.n_moving > 0) k_wall_motion<R><<<nblk(P.n_moving), 256, 0, st>>>(v, P, sb.key, t);
+void Launch<R>::wall_motion(const View<R>& v, const Params& P, const KC<R>&, SortBufs sb, double, hipStream_t st) {
+  if (P.n_moving > 0) k_wall_motion<R><<<nblk(P.n_moving), 256, 0, st>>>(v, P, sb.key);
 }
 template <typename R>
 void Launch<R>::gather(const View<R>& src, const View<R>& dst, const Params& P, SortBufs sb, hipStream_t st) {

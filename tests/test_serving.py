@@ -151,3 +151,36 @@ def test_results_alone_and_in_the_mix_are_bitwise_equal():
         mix = srv.records[r.rid].result
         for key in FIELDS + ["bodies"]:
             assert np.array_equal(alone[r.rid][key], mix[key]), (r.rid, key)
+
+
+@pytest.mark.gpu
+def test_batch_graph_replays_match_lone_steps():
+    """A batch steps through captured graphs after its first steps; replays
+    interleaved with eager reads give, bit for bit, the lone results."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2103_07925_amd import sphrb as B
+    reqs = _mix_requests(B)
+    n = 9
+    alone = []
+    for r in reqs:
+        g = B.SphScene(r.scene, precision=r.precision)
+        g.step(n)
+        g.sync()
+        alone.append(g.sph_scene_read_particles(FIELDS))
+        g.close()
+    scenes = [B.SphScene(r.scene, precision=r.precision) for r in reqs]
+    bt = B.SphBatch(scenes, stream=torch.cuda.Stream())    # graphs need a stream of its own
+    bt.step(3)
+    mid = scenes[0].sph_scene_read_particles(["X"])      # eager work between replays
+    assert np.all(np.isfinite(mid["X"]))
+    bt.step(2)
+    scenes[1].sync()
+    bt.step(n - 5)
+    for sc, ref in zip(scenes, alone):
+        sc.sync()
+        got = sc.sph_scene_read_particles(FIELDS)
+        for key in FIELDS:
+            assert np.array_equal(ref[key], got[key]), key
+        assert sc.stats().step == n
