@@ -293,6 +293,8 @@ void carve(Carver& cv, sph_scene* s, const Params& P, int64_t nmat) {
   s->nb.ent = cv.take<uint16_t>((size_t)P.max_waves * cap * 64);
   s->nb.cnt = cv.take<uint8_t>((size_t)P.max_waves * 64);
   s->nb.split = cv.take<uint8_t>((size_t)P.max_waves * 64);
+  s->nb.ext = cv.take<uint32_t>((size_t)P.ext_cap);
+  s->nb.ext_n = cv.take<uint32_t>(4);
   s->nb.jlo = cv.take<uint32_t>((size_t)P.max_waves * nsr);
   s->wcount = cv.take<uint32_t>((size_t)P.nrows);
   s->woff = cv.take<uint32_t>((size_t)P.nrows + 1);
@@ -403,6 +405,7 @@ int make_params(const sph_scene_desc* d, Params& P, double* m_min) {
   // with phase switching every particle may become rigid and every body
   // slot up to max_bodies may be in use
   P.slot_cap = P.pswitch ? P.n : P.n_rigid;
+  P.ext_cap = std::min<int64_t>(P.n, c.n_wall + P.slot_cap);
   P.body_launch = P.pswitch ? P.maxb : P.nb;
   *m_min = mmin;
   return SPH_OK;
@@ -884,6 +887,7 @@ int create_impl(const sph_scene_desc* d, sph_scene* s) {
   zero_pairs(s, true);
   launch_fill_u32(reinterpret_cast<uint32_t*>(s->dstep), 0u, 2, st);
   launch_fill_u32(s->sb.ccount, 0u, P.ncells, st);
+  launch_fill_u32(s->nb.ext_n, 0u, 1, st);
   s->ip = 0;
   s->iu = 0;
   s->iT = 0;

@@ -68,6 +68,7 @@ struct Params {
   int64_t nrows, max_waves;
   int64_t slot_cap;     // rigid slot capacity (all particles when phases switch)
   int body_launch;      // bodies covered by body kernels (capacity when phases switch)
+  int64_t ext_cap;      // wall and rigid particles at most (extrapolation targets)
 };
 
 // one wavefront of the sweeps: up to 64 consecutive sorted particles of one
@@ -86,6 +87,8 @@ struct Lists {
   uint8_t* cnt;        // entries of every lane (self included), [wave][lane]
   uint8_t* split;      // entries in canonical order from the front; wall and rigid
                        // lanes: their fluid neighbours (the rest from the end)
+  uint32_t* ext;       // wall and rigid particles as (wave << 6 | lane), any order
+  uint32_t* ext_n;     // their number
   uint32_t* jlo;
 };
 

@@ -256,9 +256,11 @@ __device__ __forceinline__ MatL<R> mat_of(const MatL<R>* sm, const View<R>& v, u
 // wall / rigid extrapolation (local force balance of Adami et al. 2012):
 // p_w = [sum p_f W + sum rho_f (b_f - a_w).(x_w - x_f) W] / sum W,
 // u~_w = 2 u_w - sum u_f W / sum W; returns the number of fluid neighbours
-template <typename R, int DIM, typename It>
+// SUB lanes share a target (each takes every SUB-th neighbour); their
+// partial sums are combined in a fixed order and the first lane writes
+template <typename R, int DIM, int SUB, typename It>
 __device__ __forceinline__ uint32_t extrap_one(const View<R>& v, const KC<R>& k, const MatL<R>* sm, uint32_t i,
-                                               bool act, It&& it) {
+                                               bool act, bool writer, It&& it) {
   const uint32_t inf = v.info[i];
   const uint32_t kind = ikind(inf);
   R aw[3] = {R(0), R(0), R(0)};
@@ -298,7 +300,15 @@ __device__ __forceinline__ uint32_t extrap_one(const View<R>& v, const KC<R>& k,
       if (DIM == 3) su2 = kfma(nb.vp.z, W, su2);
     }
   });
-  if (!act) return 0;
+  for (int off = 1; off < SUB; off <<= 1) {
+    sW = sW + __shfl_xor(sW, off, 64);
+    sp = sp + __shfl_xor(sp, off, 64);
+    su0 = su0 + __shfl_xor(su0, off, 64);
+    su1 = su1 + __shfl_xor(su1, off, 64);
+    su2 = su2 + __shfl_xor(su2, off, 64);
+    c = c + __shfl_xor(c, off, 64);
+  }
+  if (!act || !writer) return 0;
   const V4<R> ui = v.u[i];
   V4<R> o;
   R pw;
@@ -640,16 +650,20 @@ struct NbRec {
   V4<R> a, vp, rm;
 };
 
+// gl: the lane's column of its wave's list block; jl: the stencil-row bases
+// of the lane's wave; cx_first: the first cell of the lane's wave (frame)
+// (entries q0, q0 + dq, ... of the first n_lane)
 template <typename R, int DIM, bool PACKED, typename F>
-__device__ __forceinline__ void for_list(const View<R>& v, const KC<R>& k, const MatL<R>* sm, const WaveGeo& g,
-                                         const uint32_t* jl, int w, int n_lane, int split, uint32_t i,
-                                         const V4<R>& T, bool with_self, F&& visit) {
+__device__ __forceinline__ void for_list(const View<R>& v, const KC<R>& k, const MatL<R>* sm, int cx_first,
+                                         const uint32_t* jl, const uint16_t* gl, int n_all, int split, uint32_t i,
+                                         const V4<R>& T, bool with_self, F&& visit, int q0 = 0, int dq = 1) {
   constexpr int CAP = Nb<DIM>::cap;
   constexpr bool PK = PACKED && !IsExact<R>::v;
-  const uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + threadIdx.x;
+  const int n_lane = n_all > q0 ? (n_all - q0 + dq - 1) / dq : 0;   // this lane's entries
   const int nmax = wave_max_i(n_lane);
   // streamed once: kept out of the L1, which holds the gathered records
-  auto entry = [&](int q) -> uint32_t {
+  auto entry = [&](int t) -> uint32_t {
+    const int q = q0 + t * dq;
     const int at = q < split ? q : CAP - 1 - (q - split);
     return __builtin_nontemporal_load(gl + (size_t)at * 64);
   };
@@ -706,7 +720,7 @@ __device__ __forceinline__ void for_list(const View<R>& v, const KC<R>& k, const
           pj = r0.a;
           nb.rm = r0.rm;
         }
-        const V4<R> sj = to_frame<R>(pj, k, g.cx_first, dy, dz);
+        const V4<R> sj = to_frame<R>(pj, k, cx_first, dy, dz);
         R d0, d1, d2;
         const R r2 = dist2<R, DIM>(T, sj, d0, d1, d2);
         visit(nb, d0, d1, d2, r2);
@@ -872,6 +886,17 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
   if (overflow && active) set_err(v.err, ERR_NBCAP);
   const int cnt = active ? nf + nb : 0;
   v.nb.cnt[(size_t)w * 64 + lane] = (uint8_t)cnt;
+  // wall and rigid lanes join the compact extrapolation list
+  const unsigned long long pm = __ballot(part);
+  if (pm) {
+    uint32_t base = 0u;
+    if (lane == 0) base = atomicAdd(v.nb.ext_n, (uint32_t)__popcll(pm));
+    base = __shfl(base, 0, 64);
+    if (part) {
+      const uint32_t below = (uint32_t)__popcll(pm & ((1ull << lane) - 1ull));
+      v.nb.ext[base + below] = ((uint32_t)w << 6) | (uint32_t)lane;
+    }
+  }
   v.nb.split[(size_t)w * 64 + lane] = (uint8_t)(active ? nf : 0);
   unsigned long long pairs = 0;
   if (active) {
@@ -918,37 +943,52 @@ __global__ void __launch_bounds__(64) k_build_density(View<R> v, Params P, KC<R>
   build_density_wave<R, DIM>(v, P, k, xcd_wave(blockIdx.x, gridDim.x));
 }
 
+// Extrapolation runs over the compact list of wall and rigid particles the
+// list build appends (wave << 6 | lane), 64 targets per workgroup, one lane
+// each, whatever share of a target's wave was fluid; workgroups stride over
+// the list.  (Splitting a target over several lanes makes each list-entry
+// load touch several rows of the [entry][lane] layout: slower.)
+template <typename R> struct ExtSub { static constexpr int v = 1; };
+
 template <typename R, int DIM>
-__device__ __forceinline__ void extrapolate_wave(const View<R>& v, const Params& P, const KC<R>& k, int w) {
-  __shared__ uint32_t jl[Nb<DIM>::rows];
-  if (w >= (int)*v.nb.nwaves) return;
-  const WaveInfo wi = v.nb.table[w];
-  const int lane = threadIdx.x;
-  const bool active = lane < (int)wi.cnt;
-  const uint32_t i = wi.p0 + (active ? (uint32_t)lane : 0u);
-  const uint32_t kind = ikind(v.info[i]);
-  const bool need = active && kind != KF;
-  if (!__any(need)) return;
+__device__ __forceinline__ void extrapolate_wave(const View<R>& v, const Params& P, const KC<R>& k, int blk,
+                                                 int nblk) {
+  constexpr int NR = Nb<DIM>::rows, CAP = Nb<DIM>::cap;
+  constexpr int kExtSub = ExtSub<R>::v, kExtPerBlock = 64 / kExtSub;
+  __shared__ uint32_t jls[64 * NR];
+  const uint32_t total = *v.nb.ext_n;
+  if ((uint32_t)blk * kExtPerBlock >= total) return;
   __shared__ MatL<R> smat[kMatLds];
   stage_mats<R>(smat, v, P);
-  stage_jlo<DIM>(jl, v.nb, w);
-  const WaveGeo g = wave_geo<R>(v, P, wi);
-  const V4<R> T = to_frame<R>(v.pos[i], k, g.cx_first, 0, 0);
-  // fluid neighbours only: the first split entries of a wall / rigid lane
-  const int n_lane = need ? (int)v.nb.split[(size_t)w * 64 + lane] : 0;
-  unsigned long long cr = 0, cw = 0;
-  const uint32_t c = extrap_one<R, DIM>(v, k, smat, i, need, [&](bool ws, auto&& f) {
-    for_list<R, DIM, true>(v, k, smat, g, jl, w, n_lane, n_lane, i, T, ws, f);
-  });
-  if (need && kind == KR) cr = c;
-  else if (need) cw = c;
-  block_add_pairs(v.pairs, cr, 3);
-  block_add_pairs(v.pairs, cw, 4);
+  const int lane = threadIdx.x, sub = lane & (kExtSub - 1);
+  for (uint32_t b = (uint32_t)blk; b * kExtPerBlock < total; b += (uint32_t)nblk) {
+    const uint32_t slot = b * kExtPerBlock + (uint32_t)(lane / kExtSub);
+    const bool need = slot < total;
+    const uint32_t e = v.nb.ext[need ? slot : b * kExtPerBlock];
+    const int w = (int)(e >> 6), l = (int)(e & 63u);
+    const WaveInfo wi = v.nb.table[w];
+    const uint32_t i = wi.p0 + (uint32_t)l;
+    const uint32_t kind = ikind(v.info[i]);
+    for (int rr = 0; rr < NR; ++rr) jls[lane * NR + rr] = v.nb.jlo[(size_t)w * NR + rr];
+    const WaveGeo g = wave_geo<R>(v, P, wi);
+    const V4<R> T = to_frame<R>(v.pos[i], k, g.cx_first, 0, 0);
+    // fluid neighbours only: the first split entries of a wall / rigid lane
+    const int n_f = need ? (int)v.nb.split[(size_t)w * 64 + l] : 0;
+    unsigned long long cr = 0, cw = 0;
+    const uint32_t c = extrap_one<R, DIM, kExtSub>(v, k, smat, i, need, sub == 0, [&](bool ws, auto&& f) {
+      for_list<R, DIM, true>(v, k, smat, g.cx_first, jls + lane * NR, v.nb.ent + (size_t)w * CAP * 64 + l, n_f,
+                             n_f, i, T, ws, f, sub, kExtSub);
+    });
+    if (need && sub == 0 && kind == KR) cr = c;
+    else if (need && sub == 0) cw = c;
+    block_add_pairs(v.pairs, cr, 3);
+    block_add_pairs(v.pairs, cw, 4);
+  }
 }
 
 template <typename R, int DIM>
 __global__ void __launch_bounds__(64) k_extrapolate_list(View<R> v, Params P, KC<R> k) {
-  extrapolate_wave<R, DIM>(v, P, k, xcd_wave(blockIdx.x, gridDim.x));
+  extrapolate_wave<R, DIM>(v, P, k, (int)blockIdx.x, (int)gridDim.x);
 }
 
 // t = (steps begun) x dt, from the scene's device step counter
@@ -977,7 +1017,8 @@ __device__ __forceinline__ void forces_wave(const View<R>& v, const Params& P, c
   const int split = v.nb.split[(size_t)w * 64 + lane];
   const double t = (double)(*v.dstep) * P.dt;
   forces_one<R, DIM, THERMAL>(v, P, k, smat, i, need, kick, heat, t, [&](bool ws, auto&& f) {
-    for_list<R, DIM, THERMAL == 0>(v, k, smat, g, jl, w, n_lane, split, i, T, ws, f);
+    for_list<R, DIM, THERMAL == 0>(v, k, smat, g.cx_first, jl, v.nb.ent + (size_t)w * Nb<DIM>::cap * 64 + lane,
+                                   n_lane, split, i, T, ws, f);
   });
 }
 
@@ -1019,7 +1060,7 @@ __global__ void __launch_bounds__(64) k_extrapolate_batch(const Slot<R>* tab, in
   const View<R> v = S.v;
   const Params P = S.P;
   const KC<R> k = S.k;
-  extrapolate_wave<R, DIM>(v, P, k, xcd_wave((int)(blockIdx.x - S.b0), (int)S.nb));
+  extrapolate_wave<R, DIM>(v, P, k, (int)(blockIdx.x - S.b0), (int)S.nb);
 }
 
 template <typename R, int DIM, int THERMAL>
@@ -1091,6 +1132,7 @@ __global__ void __launch_bounds__(256) k_kick_drift(View<R> v, Params P, KC<R> k
     v.pairs[3] = 0ull;
     v.pairs[4] = 0ull;
     v.dstep[0] = v.dstep[0] + 1ull;
+    *v.nb.ext_n = 0u;
   }
   if (i >= P.n) return;
   const uint32_t inf = v.info[i];
@@ -1935,7 +1977,8 @@ void Launch<R>::density(const View<R>& v, const Params& P, const KC<R>& k, hipSt
 template <typename R>
 void Launch<R>::extrapolate(const View<R>& v, const Params& P, const KC<R>& k, hipStream_t st) {
   if (P.n <= 0) return;
-  const unsigned g = (unsigned)P.max_waves;
+  const unsigned g = nblk(P.ext_cap, 64 / ExtSub<R>::v);
+  if (g == 0) return;
   if (P.dim == 2) k_extrapolate_list<R, 2><<<g, 64, 0, st>>>(v, P, k);
   else k_extrapolate_list<R, 3><<<g, 64, 0, st>>>(v, P, k);
 }
