@@ -286,7 +286,7 @@ void carve(Carver& cv, sph_scene* s, const Params& P, int64_t nmat) {
   s->bodies = cv.take<Body>((size_t)std::max(P.maxb, 1));
   s->mat = cv.take<MatT<R>>((size_t)nmat);
   s->err = cv.take<uint32_t>(4);
-  s->pairs = cv.take<unsigned long long>(6);
+  s->pairs = cv.take<unsigned long long>((size_t)kPairWords);
   // compact neighbour lists: one slot per possible wave
   const int cap = 192, nsr = P.dim == 3 ? 9 : 3;
   s->nb.table = cv.take<WaveInfo>((size_t)P.max_waves);
@@ -483,11 +483,17 @@ View<R> cur(sph_scene* s) {
 }
 
 // clear the per-evaluation pair counters (and the running total)
-void zero_pairs(sph_scene* s, bool total) {
-  uint32_t* p = reinterpret_cast<uint32_t*>(s->pairs);
-  launch_fill_u32(p, 0u, 2, s->stream);
-  launch_fill_u32(p + 4, 0u, 6, s->stream);
-  if (total) launch_fill_u32(p + 2, 0u, 2, s->stream);
+void zero_pairs(sph_scene* s, bool total) { launch_zero_pairs(s->pairs, true, total, s->stream); }
+
+// the pair counters: every counter summed over its parts
+int read_pairs(sph_scene* s, unsigned long long out[kPairSlots]) {
+  std::vector<unsigned long long> w((size_t)kPairWords);
+  HIP_TRY(hipMemcpy(w.data(), s->pairs, sizeof(unsigned long long) * w.size(), hipMemcpyDeviceToHost));
+  for (int slot = 0; slot < kPairSlots; ++slot) {
+    out[slot] = 0ull;
+    for (int p = 0; p < kPairParts; ++p) out[slot] += w[(size_t)pair_at(slot, p)];
+  }
+  return SPH_OK;
 }
 
 // counting sort by (cell, id) of the current buffers into the other set
@@ -906,7 +912,7 @@ int create_impl(const sph_scene_desc* d, sph_scene* s) {
   HIP_TRY(hipMemcpy(&err, s->err, 4, hipMemcpyDeviceToHost));
   if (err) return fail(SPH_E_STATE, "device error during set-up: " + std::to_string(err));
   // the running pair total counts steps only
-  launch_fill_u32(reinterpret_cast<uint32_t*>(s->pairs + 1), 0u, 2, st);
+  launch_zero_pairs(s->pairs, false, true, st);
   HIP_TRY(hipStreamSynchronize(st));
   return SPH_OK;
 }
@@ -1403,11 +1409,11 @@ int sph_scene_read_stats(sph_scene* s, sph_stats* o) {
   if (s->precision == SPH_FP64) Launch<double>::global_sums(cur<double>(s), P, s->gpart, kGlobalBlocks, s->gout, s->stream);
   else Launch<float>::global_sums(cur<float>(s), P, s->gpart, kGlobalBlocks, s->gout, s->stream);
   HIP_TRY(hipStreamSynchronize(s->stream));
-  unsigned long long pr[6];
+  unsigned long long pr[kPairSlots];
   uint32_t err = 0;
   double g[6];
   uint32_t dyn[4];
-  HIP_TRY(hipMemcpy(pr, s->pairs, sizeof(pr), hipMemcpyDeviceToHost));
+  if (int e = read_pairs(s, pr)) return e;
   HIP_TRY(hipMemcpy(&err, s->err, 4, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(g, s->gout, sizeof(g), hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(dyn, s->dyn, sizeof(dyn), hipMemcpyDeviceToHost));

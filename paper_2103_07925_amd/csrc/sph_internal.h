@@ -15,6 +15,15 @@
 
 namespace sphrb {
 
+// Pair counters: kPairSlots counters ([0] last evaluation, [1] running
+// total, [2] fluid targets, [3] fluid neighbours of rigid targets, [4] fluid
+// neighbours of walls), each spread over kPairParts partial sums kPairStride
+// words apart (one cache line each), so that the waves of a sweep do not
+// all update one address; a counter's value is the sum of its parts.
+constexpr int kPairSlots = 5, kPairParts = 32, kPairStride = 16;
+constexpr int kPairWords = kPairSlots * kPairParts * kPairStride;
+__host__ __device__ inline int pair_at(int slot, int part) { return (slot * kPairParts + part) * kPairStride; }
+
 template <typename R>
 struct alignas(16) V4 {
   R x, y, z, w;
@@ -170,7 +179,7 @@ struct View {
   Body* bodies;
   // counters
   uint32_t* err;
-  unsigned long long* pairs;   // [0] last evaluation, [1] running total, [2..4] by target kind
+  unsigned long long* pairs;   // kPairWords: spread pair counters (pair_at)
   Lists nb;
   uint32_t* dyn;               // [0] rigid particles, [1] bodies (change with phase switches)
   unsigned long long* dstep;   // steps begun (the step being taken, from 1)
@@ -221,6 +230,7 @@ struct Launch {
 // precision-independent launchers
 void launch_fill_u32(uint32_t* p, uint32_t val, int64_t n, hipStream_t st);
 void launch_step_begin(unsigned long long* pairs, unsigned long long* dstep, hipStream_t st);
+void launch_zero_pairs(unsigned long long* pairs, bool eval, bool total, hipStream_t st);
 // gate (may be NULL): the scan is skipped when gate[0] == 0
 void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum, hipStream_t st,
                      const uint32_t* gate = nullptr);

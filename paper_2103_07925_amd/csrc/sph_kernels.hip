@@ -194,14 +194,25 @@ __device__ __forceinline__ void get_pos(const Params& P, const View<R>& v, int64
   }
 }
 
-// pair counters: [0] last evaluation, [1] running total, [2] fluid targets,
-// [3] fluid neighbours of rigid targets, [4] fluid neighbours of walls
-__device__ __forceinline__ void block_add_pairs(unsigned long long* pairs, unsigned long long cnt, int slot) {
+// a wave's pair count into the last-evaluation, running-total and per-kind
+// counters, in the partial sums of part `part` (the caller's wave or block
+// index, so that concurrent waves mostly update different parts)
+__device__ __forceinline__ void block_add_pairs(unsigned long long* pairs, unsigned long long cnt, int slot,
+                                                int part) {
   for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
   if ((threadIdx.x & 63) == 0 && cnt) {
-    atomicAdd(&pairs[0], cnt);
-    atomicAdd(&pairs[1], cnt);
-    atomicAdd(&pairs[slot], cnt);
+    const int pt = part & (kPairParts - 1);
+    atomicAdd(&pairs[pair_at(0, pt)], cnt);
+    atomicAdd(&pairs[pair_at(1, pt)], cnt);
+    atomicAdd(&pairs[pair_at(slot, pt)], cnt);
+  }
+}
+// per-evaluation counters (all but the running total) to zero; thread t of
+// nt threads clears every nt-th part
+__device__ __forceinline__ void clear_eval_pairs(unsigned long long* pairs, int t, int nt) {
+  for (int q = t; q < 4 * kPairParts; q += nt) {
+    const int slot = q / kPairParts;
+    pairs[pair_at(slot == 0 ? 0 : slot + 1, q % kPairParts)] = 0ull;
   }
 }
 
@@ -935,7 +946,7 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
     rm.w = P.thermal ? v.T[i] : R(0);
     v.rm[i] = rm;
   }
-  block_add_pairs(v.pairs, pairs, 2);
+  block_add_pairs(v.pairs, pairs, 2, w);
 }
 
 template <typename R, int DIM>
@@ -981,8 +992,8 @@ __device__ __forceinline__ void extrapolate_wave(const View<R>& v, const Params&
     });
     if (need && sub == 0 && kind == KR) cr = c;
     else if (need && sub == 0) cw = c;
-    block_add_pairs(v.pairs, cr, 3);
-    block_add_pairs(v.pairs, cw, 4);
+    block_add_pairs(v.pairs, cr, 3, (int)b);
+    block_add_pairs(v.pairs, cw, 4, (int)b);
   }
 }
 
@@ -1074,13 +1085,13 @@ __global__ void __launch_bounds__(64) k_forces_batch(const Slot<R>* tab, int ns,
 
 // start of a step: per-evaluation pair counters cleared, step counter advanced
 __global__ void __launch_bounds__(64) k_step_begin(unsigned long long* pairs, unsigned long long* dstep) {
-  if (threadIdx.x == 0) {
-    pairs[0] = 0ull;
-    pairs[2] = 0ull;
-    pairs[3] = 0ull;
-    pairs[4] = 0ull;
-    dstep[0] = dstep[0] + 1ull;
-  }
+  clear_eval_pairs(pairs, (int)threadIdx.x, 64);
+  if (threadIdx.x == 0) dstep[0] = dstep[0] + 1ull;
+}
+// pair counters to zero: the per-evaluation ones and / or the running total
+__global__ void __launch_bounds__(256) k_zero_pairs(unsigned long long* pairs, int eval, int total) {
+  if (eval) clear_eval_pairs(pairs, (int)threadIdx.x, 256);
+  if (total && (int)threadIdx.x < kPairParts) pairs[pair_at(1, (int)threadIdx.x)] = 0ull;
 }
 
 // neighbour export from the lists (diagnostic): counts, then ids
@@ -1122,15 +1133,12 @@ __global__ void __launch_bounds__(64) k_list_fill(View<R> v, Params P, const uin
 // ---------------------------------------------------------------------------
 
 // first kick and drift of fluid particles, new cell keys of every particle
-// (the first thread also starts the step: pair counters, step counter)
+// (the first workgroup also starts the step: pair counters, step counter)
 template <typename R>
 __global__ void __launch_bounds__(256) k_kick_drift(View<R> v, Params P, KC<R> k, uint32_t* key) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0) clear_eval_pairs(v.pairs, (int)threadIdx.x, 256);
   if (i == 0) {
-    v.pairs[0] = 0ull;
-    v.pairs[2] = 0ull;
-    v.pairs[3] = 0ull;
-    v.pairs[4] = 0ull;
     v.dstep[0] = v.dstep[0] + 1ull;
     *v.nb.ext_n = 0u;
   }
@@ -1883,6 +1891,9 @@ void launch_fill_u32(uint32_t* p, uint32_t val, int64_t n, hipStream_t st) {
 
 void launch_step_begin(unsigned long long* pairs, unsigned long long* dstep, hipStream_t st) {
   k_step_begin<<<1, 64, 0, st>>>(pairs, dstep);
+}
+void launch_zero_pairs(unsigned long long* pairs, bool eval, bool total, hipStream_t st) {
+  k_zero_pairs<<<1, 256, 0, st>>>(pairs, eval ? 1 : 0, total ? 1 : 0);
 }
 
 void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum, hipStream_t st,
