@@ -280,16 +280,21 @@ def main():
     }
 
     if args.other_steps > 0:
-        c3 = S.config_c3(seed=args.seed, nsites=(100, 100, 50), n_grains=250)
-        c4 = S.config_c4(seed=args.seed, nsites=(200, 100, 50), n_frag=62)
+        c3 = S.config_c3(seed=args.seed)
         out["other_workloads"] = [
             timed_workload(B, c3, args.other_steps,
                            "two-phase thermal grains with conduction, moving heat source and phase switching, "
-                           "1/8 of the 200x200x100-site box (100x100x50 sites, 250 grains requested)"),
-            timed_workload(B, c4, args.other_steps,
-                           "container with a moving perforated wall plate and 2-6-sphere fragments in contact, "
-                           "1/8 of the 400x200x100-site box (200x100x50 sites, 62 fragments)"),
+                           "200x200x100 fluid sites, 2000 grains requested (log-normal radii, median 4.3 dx)"),
         ]
+        del c3
+        torch.cuda.empty_cache()
+        c4 = S.config_c4(seed=args.seed)
+        out["other_workloads"].append(
+            timed_workload(B, c4, args.other_steps,
+                           "container with a moving perforated wall plate and 500 fragments of 2-6 spheres in "
+                           "contact, 400x200x100 fluid sites"))
+        del c4
+        torch.cuda.empty_cache()
     if args.serve_scenes > 0:
         out["serving"] = serving_run(args.serve_scenes, args.seed)
         torch.cuda.empty_cache()

@@ -141,6 +141,27 @@ def in_ball(x: np.ndarray, centre, radius: float, dim: int) -> np.ndarray:
     return np.sum(d * d, axis=1) <= radius * radius
 
 
+def ball_sites(nsites, dx: float, dim: int, centre, radius: float) -> np.ndarray:
+    """Indices of the sites of the lattice `lattice_sites(dim, 0, nsites, dx)`
+    that are inside the ball (the same test as `in_ball`), found from the
+    ball's bounding box of lattice indices rather than by testing every site."""
+    c = np.asarray(centre, dtype=np.float64)
+    rng_ = []
+    for a in range(dim):
+        m0 = max(0, int(math.floor((c[a] - radius) / dx - 0.5)) - 1)
+        m1 = min(int(nsites[a]), int(math.ceil((c[a] + radius) / dx - 0.5)) + 2)
+        rng_.append(np.arange(m0, max(m0, m1), dtype=np.int64))
+    if dim == 2:
+        gy, gx = np.meshgrid(rng_[1], rng_[0], indexing="ij")
+        idx = (gx + int(nsites[0]) * gy).ravel()
+        pts = np.stack([(gx.ravel() + 0.5) * dx, (gy.ravel() + 0.5) * dx, np.zeros(gx.size)], axis=1)
+    else:
+        gz, gy, gx = np.meshgrid(rng_[2], rng_[1], rng_[0], indexing="ij")
+        idx = (gx + int(nsites[0]) * (gy + int(nsites[1]) * gz)).ravel()
+        pts = np.stack([(gx.ravel() + 0.5) * dx, (gy.ravel() + 0.5) * dx, (gz.ravel() + 0.5) * dx], axis=1)
+    return idx[in_ball(pts, c, radius, dim)]
+
+
 def _assemble(name, dim, dx, lo, hi, groups, materials, bodies, **kw) -> Scene:
     """groups: list of (positions, kind, phase, body, moving, T) tuples."""
     xs, kinds, phases, bids, movs, Ts = [], [], [], [], [], []
@@ -270,7 +291,8 @@ def config_c3(seed: int = 0, nsites=(200, 200, 100), dx: float = 0.1, n_grains: 
               rho_gas: float = 1e-3, p0: float = 100.0) -> Scene:
     """Two-phase liquid/gas box with a temperature field and heat conduction:
     rigid grains (solid metal, rho = 1, cp = 1, kappa = 10) with log-normal
-    radii placed by random sequential addition in the lower 75 % of the box,
+    radii placed by random sequential addition (largest first, gap dx, at
+    most 200 tries per grain on average) in the lower 75 % of the box,
     the rest gas (cp = 0.01, kappa = 0.1, density ratio 1000, viscosity ratio
     100 against the liquid metal phase).  Transition temperature 50; grains
     start at 25, gas at 50; a Gaussian surface heat source moves along x.
@@ -290,11 +312,15 @@ def config_c3(seed: int = 0, nsites=(200, 200, 100), dx: float = 0.1, n_grains: 
     kind_of = np.full(inner.shape[0], FLUID, np.int32)
     phase_of = np.full(inner.shape[0], 2, np.int32)
     body_of = np.full(inner.shape[0], -1, np.int32)
-    radii = lognormal_radii(rng, n_grains, median_r * dx, sigma_r)
+    # largest first: random sequential addition then packs closer to the
+    # intended solid fraction before it jams
+    radii = np.sort(lognormal_radii(rng, n_grains, median_r * dx, sigma_r))[::-1]
     centres = []
     bodies = []
     upper = 0.75 * ext[dim - 1]
     tries = 0
+    placed = np.zeros((n_grains, dim))
+    placed_r = np.zeros(n_grains)
     for R in radii:
         while True:
             tries += 1
@@ -304,17 +330,17 @@ def config_c3(seed: int = 0, nsites=(200, 200, 100), dx: float = 0.1, n_grains: 
             for a in range(dim):
                 top = upper if a == dim - 1 else ext[a]
                 cpos[a] = rng.uniform(R + 2 * dx, top - R - 2 * dx) if top - R - 2 * dx > R + 2 * dx else 0.5 * top
-            ok = True
-            for (cc, rr) in centres:
-                if np.sum((cc[:dim] - cpos[:dim]) ** 2) < (rr + R + dx) ** 2:
-                    ok = False
-                    break
-            if ok:
+            k = len(centres)
+            d2 = np.sum((placed[:k] - cpos[:dim]) ** 2, axis=1)
+            if not np.any(d2 < (placed_r[:k] + R + dx) ** 2):
+                placed[k] = cpos[:dim]
+                placed_r[k] = R
                 centres.append((cpos, R))
                 break
     for k, (cpos, R) in enumerate(centres):
-        sel = in_ball(inner, cpos, R, dim) & (kind_of == FLUID)
-        if not np.any(sel):
+        idx = ball_sites(nsites, dx, dim, cpos, R)
+        sel = idx[kind_of[idx] == FLUID]
+        if sel.size == 0:
             continue
         kind_of[sel] = RIGID
         phase_of[sel] = 0
@@ -372,7 +398,7 @@ def config_c4(seed: int = 0, nsites=(400, 200, 100), dx: float = 0.1, n_frag: in
     for k in range(n_frag):
         nsph = int(rng.integers(2, 7))
         base = np.array([rng.uniform(0.05, 0.95) * ext[a] for a in range(dim)] + [0.0] * (3 - dim))
-        sel = np.zeros(inner.shape[0], bool)
+        parts = []
         r0 = rng.uniform(*r_range) * dx
         for s in range(nsph):
             R = r0 if s == 0 else rng.uniform(*r_range) * dx
@@ -380,11 +406,12 @@ def config_c4(seed: int = 0, nsites=(400, 200, 100), dx: float = 0.1, n_frag: in
             if dim == 2:
                 off[2] = 0.0
             cc = base + (off if s > 0 else 0.0)
-            sel |= in_ball(inner, cc, R, dim)
-        sel &= (kind_of == FLUID)
+            parts.append(ball_sites(nsites, dx, dim, cc, R))
+        sel = np.unique(np.concatenate(parts))
+        sel = sel[kind_of[sel] == FLUID]
         # stay clear of the plate and the walls
-        sel &= np.abs(px - xm) > 4.0 * dx
-        if np.sum(sel) < 4:
+        sel = sel[np.abs(px[sel] - xm) > 4.0 * dx]
+        if sel.size < 4:
             continue
         kind_of[sel] = RIGID
         phase_of[sel] = 2
