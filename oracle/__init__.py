@@ -21,10 +21,10 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 FLUID, WALL, RIGID = 0, 1, 2
 BODY_REC = 36
-F_X, F_U, F_A, F_RHO, F_P, F_T, F_PW, F_UW, F_FR, F_M, F_DTDT = range(11)
+F_X, F_U, F_A, F_RHO, F_P, F_T, F_PW, F_UW, F_FR, F_M, F_DTDT, F_AB, F_UD = range(13)
 I_KIND, I_PHASE, I_BODY, I_CELL = range(4)
 S_NEIGHBORS, S_DENSITY, S_EXTRAP, S_HEAT, S_FORCES, S_BODYSUMS, S_BODYACC = range(4, 11)
-_VEC_FIELDS = {F_X, F_U, F_A, F_UW, F_FR}
+_VEC_FIELDS = {F_X, F_U, F_A, F_UW, F_FR, F_AB, F_UD}
 
 
 def build(force: bool = True) -> str:
@@ -64,7 +64,8 @@ class Desc(C.Structure):
                 ("wall_A", C.c_double), ("wall_Omega", C.c_double), ("wall_dir", C.c_double * 3),
                 ("heat_src", C.c_int32), ("pad1", C.c_int32),
                 ("src_Q", C.c_double), ("src_sigma", C.c_double), ("src_s0", C.c_double * 2),
-                ("src_v", C.c_double * 2), ("src_ztop", C.c_double), ("src_depth", C.c_double)]
+                ("src_v", C.c_double * 2), ("src_ztop", C.c_double), ("src_depth", C.c_double),
+                ("p_b", C.c_double)]
 
 
 _lib = None
@@ -175,6 +176,7 @@ class _DescHolder:
             d.src_s0[a] = sc.src_s0[a]
             d.src_v[a] = sc.src_v[a]
         d.src_ztop, d.src_depth = sc.src_ztop, sc.src_depth
+        d.p_b = getattr(sc, "p_b", 0.0)
         self.desc = d
 
 

@@ -41,6 +41,7 @@ struct orc_scene {
   int64_t n;
   /* particle state, original-id order */
   double *x, *u, *a, *rho, *p, *T, *dTdt, *m, *pw, *uw, *f, *rb, *rk, *aw, *x0;
+  double *ab, *ud;   /* transport-velocity formulation: a_b and u~ - u */
   int32_t *kind, *phase, *body, *moving, *cell;
   /* cell lists: ids of cell c are cids[cstart[c] .. cstart[c+1]) ascending */
   int64_t *cstart;
@@ -61,6 +62,8 @@ struct orc_scene {
   double wall_A, wall_Om, wall_dir[3];
   int heat_src;
   double sQ, ssig, ss0[2], sv[2], sztop, sdepth;
+  int tvf;
+  double pb;
   int64_t pairs;
   /* scratch */
   nb_t *nbuf;
@@ -627,8 +630,17 @@ static int stage_heat(orc_scene *s, int update) {
  *   p~ = (rho_j p_i + rho_i p_j)/(rho_i + rho_j), eta~ = 2 eta_i eta_j/(eta_i + eta_j),
  * eta = rho0 nu of the phase.  A wall or rigid neighbour enters with its
  * extrapolated p_w and u~_w, the density rho0_i (p_w/p0_i + 1) of i's phase,
- * the mass m_i and eta_i.  Written so that F_ji = -F_ij bit for bit. */
-static void pair_force(const orc_scene *s, int64_t i, int64_t j, const double *d, double r2, double *F) {
+ * the mass m_i and eta_i.  Written so that F_ji = -F_ij bit for bit.
+ *
+ * With the transport-velocity formulation (Sec. "Momentum equation" names
+ * it and leaves its terms to Adami, Hu, Adams 2013) a fluid neighbour adds
+ * the divergence of the tensor A = rho u (u~ - u) in the same pair form,
+ *   (V_i^2 + V_j^2) dW/dr (1/2) (A_i + A_j) e_ij,
+ * where A e = rho u ((u~ - u).e); wall and rigid neighbours carry no A.
+ * *c_out receives (V_i^2 + V_j^2) dW/dr / r, the factor of the
+ * background-pressure sum. */
+static void pair_force(const orc_scene *s, int64_t i, int64_t j, const double *d, double r2, double *F,
+                       double *c_out) {
   const orc_material *Mi = &s->mat[s->phase[i]];
   double rho_i = s->rho[i], p_i = s->p[i], m_i = s->m[i];
   double eta_i = Mi->rho0 * Mi->nu;
@@ -652,6 +664,17 @@ static void pair_force(const orc_scene *s, int64_t i, int64_t j, const double *d
   double r = sqrt(r2);
   double c = vv * kdW(s, r) / r;
   for (int a = 0; a < s->dim; ++a) F[a] = c * (et * (s->u[3 * i + a] - u_j[a]) - pt * d[a]);
+  if (s->tvf && s->kind[j] == ORC_FLUID) {
+    /* (1/2)(A_i + A_j) d with A d = rho u ((u~ - u).d) */
+    double si = 0.0, sj = 0.0;
+    for (int a = 0; a < s->dim; ++a) {
+      si = si + s->ud[3 * i + a] * d[a];
+      sj = sj + s->ud[3 * j + a] * d[a];
+    }
+    double hi = 0.5 * rho_i * si, hj = 0.5 * rho_j * sj;
+    for (int a = 0; a < s->dim; ++a) F[a] = F[a] + c * (hi * s->u[3 * i + a] + hj * u_j[a]);
+  }
+  *c_out = c;
 }
 
 /* Eq. nummeth_fluid_momentum for fluid particles, a_i = (1/m_i) sum_j F_ij
@@ -663,19 +686,28 @@ static void pair_force(const orc_scene *s, int64_t i, int64_t j, const double *d
 static int stage_forces(orc_scene *s) {
   double dx2 = s->dx * s->dx;
   for (int64_t i = 0; i < s->n; ++i) {
+    for (int a = 0; a < 3; ++a) s->ab[3 * i + a] = 0.0;
     if (s->kind[i] == ORC_WALL) continue;
     int64_t cnt = gather(s, i, 0);
     double acc[3] = {0.0, 0.0, 0.0};
     if (s->kind[i] == ORC_FLUID) {
+      /* background-pressure acceleration of the transport velocity,
+       * a_b = -(p_b/m_i) sum_j (V_i^2 + V_j^2) dW/dr e_ij over all neighbours */
+      double bs[3] = {0.0, 0.0, 0.0};
       for (int64_t k = 0; k < cnt; ++k) {
         const nb_t *e = &s->nbuf[k];
         if (e->r2 == 0.0) return ORC_E_STATE;
-        double F[3];
-        pair_force(s, i, e->j, e->d, e->r2, F);
-        for (int a = 0; a < s->dim; ++a) acc[a] = acc[a] + F[a];
+        double F[3], c;
+        pair_force(s, i, e->j, e->d, e->r2, F, &c);
+        for (int a = 0; a < s->dim; ++a) {
+          acc[a] = acc[a] + F[a];
+          bs[a] = bs[a] + c * e->d[a];
+        }
       }
       const orc_material *M = &s->mat[s->phase[i]];
       for (int a = 0; a < s->dim; ++a) s->a[3 * i + a] = acc[a] / s->m[i] + M->b[a];
+      if (s->tvf)
+        for (int a = 0; a < s->dim; ++a) s->ab[3 * i + a] = -(s->pb * bs[a]) / s->m[i];
     } else {
       for (int64_t k = 0; k < cnt; ++k) {
         const nb_t *e = &s->nbuf[k];
@@ -683,8 +715,8 @@ static int stage_forces(orc_scene *s) {
         if (e->r2 == 0.0) return ORC_E_STATE;
         if (s->kind[j] == ORC_FLUID) {
           double dj[3] = {-e->d[0], -e->d[1], -e->d[2]};
-          double F[3];
-          pair_force(s, j, i, dj, e->r2, F);
+          double F[3], c;
+          pair_force(s, j, i, dj, e->r2, F, &c);
           for (int a = 0; a < s->dim; ++a) acc[a] = acc[a] - F[a];
         } else if (s->contact && e->r2 < dx2 &&
                    (s->kind[j] == ORC_WALL || s->body[j] != s->body[i])) {
@@ -1019,7 +1051,7 @@ void orc_destroy(orc_scene *s) {
   if (!s) return;
   double *dp[] = {s->x, s->u, s->a, s->rho, s->p, s->T, s->dTdt, s->m, s->pw, s->uw, s->f, s->rb,
                   s->rk, s->aw, s->x0, s->bm, s->br, s->bq, s->bu, s->bw, s->ba, s->bal, s->bf,
-                  s->bt, s->bIb, s->bb, s->tmp};
+                  s->bt, s->bIb, s->bb, s->tmp, s->ab, s->ud};
   for (size_t k = 0; k < sizeof(dp) / sizeof(dp[0]); ++k) free(dp[k]);
   free(s->kind); free(s->phase); free(s->body); free(s->moving); free(s->cell);
   free(s->cstart); free(s->cids); free(s->mat); free(s->bfixed); free(s->bactive);
@@ -1080,6 +1112,7 @@ int orc_create(const orc_desc *d, orc_scene **out) {
   s->x = (double *)malloc(v3); s->u = (double *)malloc(v3); s->a = (double *)calloc(1, v3);
   s->uw = (double *)calloc(1, v3); s->f = (double *)calloc(1, v3); s->rb = (double *)calloc(1, v3);
   s->rk = (double *)calloc(1, v3); s->aw = (double *)calloc(1, v3); s->x0 = (double *)malloc(v3);
+  s->ab = (double *)calloc(1, v3); s->ud = (double *)calloc(1, v3);
   s->rho = (double *)calloc(1, v1); s->p = (double *)calloc(1, v1); s->T = (double *)malloc(v1);
   s->dTdt = (double *)calloc(1, v1); s->m = (double *)malloc(v1); s->pw = (double *)calloc(1, v1);
   s->kind = (int32_t *)malloc(i1); s->phase = (int32_t *)malloc(i1); s->body = (int32_t *)malloc(i1);
@@ -1099,7 +1132,7 @@ int orc_create(const orc_desc *d, orc_scene **out) {
   s->bb = (double *)calloc(3 * mb, sizeof(double));
   s->bfixed = (int32_t *)calloc(mb, sizeof(int32_t)); s->bactive = (int32_t *)calloc(mb, sizeof(int32_t));
   s->bstart = (int64_t *)calloc(mb + 1, sizeof(int64_t)); s->bids = (int32_t *)malloc(i1);
-  if (!s->x || !s->u || !s->a || !s->uw || !s->f || !s->rb || !s->rk || !s->aw || !s->x0 || !s->rho ||
+  if (!s->x || !s->u || !s->a || !s->ab || !s->ud || !s->uw || !s->f || !s->rb || !s->rk || !s->aw || !s->x0 || !s->rho ||
       !s->p || !s->T || !s->dTdt || !s->m || !s->pw || !s->kind || !s->phase || !s->body || !s->moving ||
       !s->cell || !s->cstart || !s->cids || !s->mat || !s->bm || !s->br || !s->bq || !s->bu || !s->bw ||
       !s->ba || !s->bal || !s->bf || !s->bt || !s->bIb || !s->bb || !s->bfixed || !s->bactive ||
@@ -1128,6 +1161,8 @@ int orc_create(const orc_desc *d, orc_scene **out) {
   s->heat_src = d->heat_src; s->sQ = d->src_Q; s->ssig = d->src_sigma;
   s->ss0[0] = d->src_s0[0]; s->ss0[1] = d->src_s0[1]; s->sv[0] = d->src_v[0]; s->sv[1] = d->src_v[1];
   s->sztop = d->src_ztop; s->sdepth = d->src_depth;
+  s->tvf = d->p_b > 0.0;
+  s->pb = s->tvf ? d->p_b : 0.0;
   /* time step and contact constants */
   double mmin;
   double dt0 = timestep_without_contact(d, &mmin);
@@ -1198,10 +1233,18 @@ static int one_step(orc_scene *s) {
       s->bw[3 * k + a] = s->bw[3 * k + a] + hdt * s->bal[3 * k + a];
     }
   }
-  /* drift */
+  /* drift; with the transport-velocity formulation fluid particles move
+   * with u~^{n+1/2} = u^{n+1/2} + (dt/2) a_b^n */
   for (int64_t i = 0; i < s->n; ++i)
     if (s->kind[i] == ORC_FLUID)
-      for (int a = 0; a < s->dim; ++a) s->x[3 * i + a] = s->x[3 * i + a] + s->dt * s->u[3 * i + a];
+      for (int a = 0; a < s->dim; ++a) {
+        double v = s->u[3 * i + a];
+        if (s->tvf) {
+          s->ud[3 * i + a] = hdt * s->ab[3 * i + a];
+          v = v + s->ud[3 * i + a];
+        }
+        s->x[3 * i + a] = s->x[3 * i + a] + s->dt * v;
+      }
   for (int k = 0; k < s->nb; ++k) {
     if (!s->bactive[k] || s->bfixed[k]) continue;
     for (int a = 0; a < 3; ++a) s->br[3 * k + a] = s->br[3 * k + a] + s->dt * s->bu[3 * k + a];
@@ -1278,6 +1321,8 @@ static double *field_ptr(const orc_scene *s, int32_t f, int *width) {
     case ORC_F_FR: *width = 3; return s->f;
     case ORC_F_M: return s->m;
     case ORC_F_DTDT: return s->dTdt;
+    case ORC_F_AB: *width = 3; return s->ab;
+    case ORC_F_UD: *width = 3; return s->ud;
     default: return NULL;
   }
 }

@@ -65,6 +65,7 @@ typedef struct {
   int32_t heat_src;
   int32_t pad1;
   double src_Q, src_sigma, src_s0[2], src_v[2], src_ztop, src_depth;
+  double p_b;                /* background pressure of the transport-velocity formulation; 0: off */
 } orc_desc;
 
 typedef struct orc_scene orc_scene;
@@ -78,7 +79,9 @@ typedef struct orc_scene orc_scene;
 /* Particle fields for orc_get / orc_set. */
 enum {
   ORC_F_X = 0, ORC_F_U = 1, ORC_F_A = 2, ORC_F_RHO = 3, ORC_F_P = 4, ORC_F_T = 5,
-  ORC_F_PW = 6, ORC_F_UW = 7, ORC_F_FR = 8, ORC_F_M = 9, ORC_F_DTDT = 10
+  ORC_F_PW = 6, ORC_F_UW = 7, ORC_F_FR = 8, ORC_F_M = 9, ORC_F_DTDT = 10,
+  ORC_F_AB = 11,   /* background-pressure acceleration of fluid particles, last evaluation */
+  ORC_F_UD = 12    /* transport minus momentum velocity u~ - u of fluid particles, last drift */
 };
 enum { ORC_I_KIND = 0, ORC_I_PHASE = 1, ORC_I_BODY = 2, ORC_I_CELL = 3 };
 

@@ -83,6 +83,7 @@ class Scene:
     src_v: tuple = (0.0, 0.0)
     src_ztop: float = 0.0
     src_depth: float = 0.0
+    p_b: float = 0.0         # background pressure of the transport-velocity formulation; 0: off
     meta: dict = field(default_factory=dict)
 
     @property
