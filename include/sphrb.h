@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 1
+#define SPH_ABI_VERSION 2
 
 enum {
   SPH_OK = 0,
@@ -109,6 +109,14 @@ typedef struct {
   int32_t heat_src;            /* Gaussian moving surface heat source */
   int32_t pad1;
   double src_Q, src_sigma, src_s0[2], src_v[2], src_ztop, src_depth;
+  /* Transport-velocity formulation (Sec. "Momentum equation" applies a
+   * constant background pressure p_b to all particles and takes the terms
+   * from Adami, Hu, Adams 2013): fluid particles drift with
+   * u~ = u + (dt/2) a_b, a_b = -(p_b/m_i) sum_j (V_i^2 + V_j^2) dW/dr e_ij
+   * over all neighbours, and fluid pairs add the divergence of
+   * A = rho u (u~ - u) to the momentum equation.  0: off (the printed
+   * momentum equation only); the paper's examples use p_b = p0. */
+  double p_b;
 } sph_scene_desc;
 
 typedef struct sph_scene sph_scene;
@@ -194,7 +202,9 @@ int sph_scene_sync(sph_scene *s);
 enum {
   SPH_F_X = 1u << 0, SPH_F_U = 1u << 1, SPH_F_A = 1u << 2, SPH_F_RHO = 1u << 3,
   SPH_F_P = 1u << 4, SPH_F_T = 1u << 5, SPH_F_PW = 1u << 6, SPH_F_UW = 1u << 7,
-  SPH_F_FR = 1u << 8, SPH_F_M = 1u << 9, SPH_F_DTDT = 1u << 10
+  SPH_F_FR = 1u << 8, SPH_F_M = 1u << 9, SPH_F_DTDT = 1u << 10,
+  SPH_F_AB = 1u << 11,   /* background-pressure acceleration a_b (fluid; 0 elsewhere or when off) */
+  SPH_F_UD = 1u << 12    /* u~ - u of the last drift (fluid; 0 elsewhere or when off) */
 };
 int sph_scene_read_particles(sph_scene *s, uint32_t field_mask, double *out_host);
 

@@ -85,7 +85,8 @@ struct sph_scene {
   uint32_t* info[2];
   int32_t* aux[2];
   int ip, iu, iT;
-  void *rho, *p, *pw, *uw, *dTdt, *vp, *rm, *pa;
+  void* ud[2];       // transport-velocity formulation: u~ - u (permuted with pos)
+  void *rho, *p, *pw, *uw, *dTdt, *vp, *rm, *pa, *ab;
   SortBufs sb;
   uint32_t* cstart;
   V4<double> *s_rb, *s_rk, *s_f, *s_aw, *s_x;
@@ -112,14 +113,16 @@ struct sph_scene {
   int64_t rec;
 };
 
-// A batch: scenes grouped by (precision, dim, thermal); each group's sweeps
+// A batch: scenes grouped by (precision, dim, mode); each group's sweeps
 // run as one launch over a table of slots in the caller's workspace.  The
 // slot table of a step depends on the scenes' buffer parities, which repeat
 // every two steps, so two tables per group are kept and re-uploaded only
 // when a scene was stepped outside the batch.
+int scene_mode(const sph_scene* s) { return (s->P.thermal ? 1 : 0) | (s->P.tvf ? 2 : 0); }
+
 struct sph_batch {
   struct Group {
-    int precision, dim, thermal;
+    int precision, dim, mode;        // mode: bit 0 thermal, bit 1 transport-velocity formulation
     std::vector<int> members;
     uint32_t blocks;
     size_t off[2];                   // table offsets in the workspace
@@ -252,7 +255,9 @@ void carve(Carver& cv, sph_scene* s, const Params& P, int64_t nmat) {
     s->id[b] = cv.take<uint32_t>(n);
     s->info[b] = cv.take<uint32_t>(n);
     s->aux[b] = cv.take<int32_t>(n);
+    s->ud[b] = P.tvf ? cv.take<V4<R>>(n) : nullptr;
   }
+  s->ab = P.tvf ? cv.take<V4<R>>(n) : nullptr;
   s->rho = cv.take<R>(n);
   s->p = cv.take<R>(n);
   s->pw = cv.take<R>(n);
@@ -394,6 +399,9 @@ int make_params(const sph_scene_desc* d, Params& P, double* m_min) {
   for (int a = 0; a < 2; ++a) { P.ss0[a] = d->src_s0[a]; P.sv[a] = d->src_v[a]; }
   P.sztop = d->src_ztop;
   P.sdepth = d->src_depth;
+  if (!(d->p_b >= 0.0) || !std::isfinite(d->p_b)) return fail(SPH_E_INVALID, "background pressure p_b must be >= 0");
+  P.tvf = d->p_b > 0.0 ? 1 : 0;
+  P.pb = P.tvf ? d->p_b : 0.0;
   P.n_mat = d->n_mat;
   P.nb = d->n_body;
   P.maxb = std::max(d->max_bodies, d->n_body);
@@ -427,6 +435,7 @@ KC<R> make_kc(const Params& P) {
   k.dc = (R)P.dc;
   k.dt = (R)P.dt;
   k.hdt = (R)P.hdt;
+  k.pb = (R)P.pb;
   for (int a = 0; a < 3; ++a) k.lo[a] = (R)P.lo[a];
   return k;
 }
@@ -443,6 +452,8 @@ View<R> make_view(sph_scene* s, int ip, int iu, int iT) {
   v.id = s->id[ip];
   v.info = s->info[ip];
   v.aux = s->aux[ip];
+  v.ud = (V4<R>*)s->ud[ip];
+  v.ab = (V4<R>*)s->ab;
   v.u_out = (V4<R>*)s->u[1 - iu];
   v.T_out = (R*)s->T[1 - iT];
   v.rho = (R*)s->rho;
@@ -622,7 +633,7 @@ int group_table(sph_batch* b, sph_batch::Group& g, int* which_out) {
 template <typename R>
 void group_sweep(sph_batch* b, sph_batch::Group& g, int which, int stage) {
   Launch<R>::batch_sweep(stage, reinterpret_cast<const Slot<R>*>(b->ws + g.off[which]), (int)g.members.size(),
-                         g.dim, g.thermal, g.blocks, 1, 1, b->stream);
+                         g.dim, g.mode, g.blocks, 1, 1, b->stream);
 }
 
 // the host-side bookkeeping of one step, without its launches (a replayed
@@ -893,6 +904,13 @@ int create_impl(const sph_scene_desc* d, sph_scene* s) {
   zero_pairs(s, true);
   launch_fill_u32(reinterpret_cast<uint32_t*>(s->dstep), 0u, 2, st);
   launch_fill_u32(s->sb.ccount, 0u, P.ncells, st);
+  if (P.tvf) {
+    // u~ - u and a_b start at zero (the first evaluation sets a_b)
+    const int64_t w = (int64_t)(sizeof(V4<R>) / 4) * P.n;
+    launch_fill_u32(reinterpret_cast<uint32_t*>(s->ud[0]), 0u, w, st);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(s->ud[1]), 0u, w, st);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(s->ab), 0u, w, st);
+  }
   launch_fill_u32(s->nb.ext_n, 0u, 1, st);
   s->ip = 0;
   s->iu = 0;
@@ -979,7 +997,7 @@ int read_particles_impl(sph_scene* s, uint32_t mask, double* out) {
   HIP_TRY(hipStreamSynchronize(st));
   std::vector<uint32_t> id(n), cell(n), info(n);
   std::vector<int32_t> aux(n);
-  std::vector<V4<R>> pos(n), u(n), a(n), uw(n);
+  std::vector<V4<R>> pos(n), u(n), a(n), uw(n), ab, ud;
   std::vector<R> rho(n), p(n), T(n), pw(n), m(n), dT(n);
   int64_t nrig = 0;
   int nbod = 0;
@@ -1000,6 +1018,12 @@ int read_particles_impl(sph_scene* s, uint32_t mask, double* out) {
     HIP_TRY(hipMemcpy(pw.data(), s->pw, sizeof(R) * n, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(m.data(), s->m[s->ip], sizeof(R) * n, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(dT.data(), s->dTdt, sizeof(R) * n, hipMemcpyDeviceToHost));
+    if (P.tvf) {
+      ab.resize(n);
+      ud.resize(n);
+      HIP_TRY(hipMemcpy(ab.data(), s->ab, sizeof(V4<R>) * n, hipMemcpyDeviceToHost));
+      HIP_TRY(hipMemcpy(ud.data(), s->ud[s->ip], sizeof(V4<R>) * n, hipMemcpyDeviceToHost));
+    }
   }
   if (nrig > 0) HIP_TRY(hipMemcpy(sf.data(), s->s_f, sizeof(V4<double>) * nrig, hipMemcpyDeviceToHost));
   double* o = out;
@@ -1049,6 +1073,15 @@ int read_particles_impl(sph_scene* s, uint32_t mask, double* out) {
   });
   if (mask & SPH_F_M) sca([&](int64_t i) { return (double)m[i]; });
   if (mask & SPH_F_DTDT) sca([&](int64_t i) { return (P.thermal && ikind(info[i]) != KW) ? (double)dT[i] : 0.0; });
+  // transport-velocity formulation, fluid particles (zero elsewhere and when off)
+  auto tv = [&](const std::vector<V4<R>>& f) {
+    vec([&](int64_t i, double* v3) {
+      const bool on = P.tvf && ikind(info[i]) == KF;
+      v3[0] = on ? (double)f[i].x : 0.0; v3[1] = on ? (double)f[i].y : 0.0; v3[2] = on ? (double)f[i].z : 0.0;
+    });
+  };
+  if (mask & SPH_F_AB) tv(ab);
+  if (mask & SPH_F_UD) tv(ud);
   return SPH_OK;
 }
 
@@ -1194,8 +1227,9 @@ int sph_scene_step(sph_scene* s, int64_t nsteps) {
 
 size_t sph_batch_bytes(int32_t n) {
   if (n <= 0) return 0;
-  // two tables per group, at most 8 groups (precision x dim x thermal)
-  return 2 * ((size_t)n * kSlotMax + 8 * 256) + 256;
+  // two tables per group, at most 16 groups (precision x dim x thermal x
+  // transport-velocity formulation)
+  return 2 * ((size_t)n * kSlotMax + 16 * 256) + 256;
 }
 
 int sph_batch_create(sph_scene* const* scenes, int32_t n, void* dev_ws, size_t ws_bytes, void* hip_stream,
@@ -1227,13 +1261,13 @@ int sph_batch_create(sph_scene* const* scenes, int32_t n, void* dev_ws, size_t w
     sph_scene* s = scenes[q];
     sph_batch::Group* g = nullptr;
     for (auto& gg : b->groups)
-      if (gg.precision == s->precision && gg.dim == s->P.dim && gg.thermal == s->P.thermal) g = &gg;
+      if (gg.precision == s->precision && gg.dim == s->P.dim && gg.mode == scene_mode(s)) g = &gg;
     if (!g) {
       b->groups.emplace_back();
       g = &b->groups.back();
       g->precision = s->precision;
       g->dim = s->P.dim;
-      g->thermal = s->P.thermal;
+      g->mode = scene_mode(s);
       g->blocks = 0;
     }
     g->members.push_back(q);

@@ -78,6 +78,8 @@ struct Params {
   int64_t slot_cap;     // rigid slot capacity (all particles when phases switch)
   int body_launch;      // bodies covered by body kernels (capacity when phases switch)
   int64_t ext_cap;      // wall and rigid particles at most (extrapolation targets)
+  int tvf;              // transport-velocity formulation on
+  double pb;            // its background pressure
 };
 
 // one wavefront of the sweeps: up to 64 consecutive sorted particles of one
@@ -104,7 +106,7 @@ struct Lists {
 // constants in the sweep precision
 template <typename R>
 struct KC {
-  R h, inv_h, wnorm, dnorm, rc2, L, dx, dx2, vol0, kc, dc, dt, hdt;
+  R h, inv_h, wnorm, dnorm, rc2, L, dx, dx2, vol0, kc, dc, dt, hdt, pb;
   R lo[3];
 };
 
@@ -145,6 +147,7 @@ struct View {
   uint32_t* id;
   uint32_t* info;
   int32_t* aux;
+  V4<R>* ud;   // transport-velocity formulation: u~ - u of the last drift (permuted)
   // outputs that are swapped in after a sweep
   V4<R>* u_out;
   R* T_out;
@@ -154,6 +157,7 @@ struct View {
   R* pw;
   V4<R>* uw;
   R* dTdt;
+  V4<R>* ab;   // transport-velocity formulation: background-pressure acceleration
   V4<R>* vp;   // neighbour record: (u, p) of fluid, (u~_w, p_w) of wall / rigid particles
   V4<R>* rm;   // neighbour record: (rho, m, info bits, T)
   V4<R>* pa;   // FP32 neighbour record: cell offsets x, y, z and packed cell x /
@@ -217,7 +221,7 @@ struct Launch {
   static void extrapolate(const View<R>& v, const Params& P, const KC<R>& k, hipStream_t st);
   static void forces(const View<R>& v, const Params& P, const KC<R>& k, int kick, int heat, hipStream_t st);
   // stage 0 density, 1 extrapolation, 2 forces, over all slots of the table
-  static void batch_sweep(int stage, const Slot<R>* tab, int ns, int dim, int thermal, uint32_t blocks, int kick,
+  static void batch_sweep(int stage, const Slot<R>* tab, int ns, int dim, int mode, uint32_t blocks, int kick,
                           int heat, hipStream_t st);
   static void rigid_velocity(const View<R>& v, const Params& P, hipStream_t st);
   static void global_sums(const View<R>& v, const Params& P, double* partials, int nblocks, double* out, hipStream_t st);

@@ -368,10 +368,11 @@ __device__ __forceinline__ R heat_source(const Params& P, double t, const double
 
 // Pair force F_ij = m_i a_ij of eq. nummeth_fluid_momentum for fluid "a"
 // against neighbour "b" (d = x_a - x_b)
+// (d = x_a - x_b); c_out receives (V_a^2 + V_b^2) dW/dr / r
 template <typename R, int DIM>
 __device__ __forceinline__ void pair_force(R rho_a, R p_a, R m_a, R eta_a, R uax, R uay, R uaz, R rho_b, R p_b,
                                            R m_b, R eta_b, R ubx, R uby, R ubz, R d0, R d1, R d2, R r, R dW,
-                                           R* F) {
+                                           R* F, R& c_out) {
   if constexpr (IsExact<R>::v) {
     const R Va = m_a / rho_a, Vb = m_b / rho_b;
     const R vv = Va * Va + Vb * Vb;
@@ -381,6 +382,7 @@ __device__ __forceinline__ void pair_force(R rho_a, R p_a, R m_a, R eta_a, R uax
     F[0] = c * (et * (uax - ubx) - pt * d0);
     F[1] = c * (et * (uay - uby) - pt * d1);
     F[2] = DIM == 3 ? c * (et * (uaz - ubz) - pt * d2) : R(0);
+    c_out = c;
   } else {
     const R Va = m_a * __builtin_amdgcn_rcpf(rho_a), Vb = m_b * __builtin_amdgcn_rcpf(rho_b);
     const R vv = kfma(Va, Va, Vb * Vb);
@@ -391,6 +393,42 @@ __device__ __forceinline__ void pair_force(R rho_a, R p_a, R m_a, R eta_a, R uax
     F[0] = c * kfma(et, uax - ubx, -pt * d0);
     F[1] = c * kfma(et, uay - uby, -pt * d1);
     F[2] = DIM == 3 ? c * kfma(et, uaz - ubz, -pt * d2) : R(0);
+    c_out = c;
+  }
+}
+
+// Transport-velocity formulation (Sec. "Momentum equation" names it and
+// leaves its terms to Adami, Hu, Adams 2013): between two fluid particles
+// the divergence of A = rho u (u~ - u) in the pair form of the momentum
+// equation, F += c (1/2) (rho_a u_a ((u~ - u)_a . d) + rho_b u_b ((u~ - u)_b . d))
+// with the c of pair_force; antisymmetric in (a, b) like the pressure term.
+template <typename R, int DIM>
+__device__ __forceinline__ void pair_stress(R c, R rho_a, const V4<R>& ua, const V4<R>& da, R rho_b, R ubx,
+                                            R uby, R ubz, const V4<R>& db, R d0, R d1, R d2, R* F) {
+  if constexpr (IsExact<R>::v) {
+    R sa = da.x * d0, sb = db.x * d0;
+    sa = sa + da.y * d1;
+    sb = sb + db.y * d1;
+    if (DIM == 3) {
+      sa = sa + da.z * d2;
+      sb = sb + db.z * d2;
+    }
+    const R ha = R(0.5) * rho_a * sa, hb = R(0.5) * rho_b * sb;
+    F[0] = F[0] + c * (ha * ua.x + hb * ubx);
+    F[1] = F[1] + c * (ha * ua.y + hb * uby);
+    if (DIM == 3) F[2] = F[2] + c * (ha * ua.z + hb * ubz);
+  } else {
+    R sa = da.x * d0, sb = db.x * d0;
+    sa = kfma(da.y, d1, sa);
+    sb = kfma(db.y, d1, sb);
+    if (DIM == 3) {
+      sa = kfma(da.z, d2, sa);
+      sb = kfma(db.z, d2, sb);
+    }
+    const R ha = R(0.5) * rho_a * sa, hb = R(0.5) * rho_b * sb;
+    F[0] = kfma(c, kfma(ha, ua.x, hb * ubx), F[0]);
+    F[1] = kfma(c, kfma(ha, ua.y, hb * uby), F[1]);
+    if (DIM == 3) F[2] = kfma(c, kfma(ha, ua.z, hb * ubz), F[2]);
   }
 }
 
@@ -429,7 +467,11 @@ __device__ __forceinline__ R inv_eos(const MatL<R>& M, R p) {
 // particles, and conduction (eq. nummeth_thermo_heat_equation), in one pass
 // over the target's neighbours.  Every lane of the wave calls it (the
 // iterator synchronises); only lanes with act set have a target.
-template <typename R, int DIM, int THERMAL, typename It>
+// With TVF the transport-velocity formulation adds the stress term between
+// fluid pairs and the background-pressure acceleration
+// a_b = -(p_b / m_i) sum_j (V_i^2 + V_j^2) dW/dr e_ij over all neighbours of
+// fluid targets.
+template <typename R, int DIM, int THERMAL, int TVF, typename It>
 __device__ __forceinline__ void forces_one(const View<R>& v, const Params& P, const KC<R>& k, const MatL<R>* sm,
                                            uint32_t i, bool act, int kick, int heat, double t, It&& it) {
   const uint32_t inf = v.info[i];
@@ -447,7 +489,10 @@ __device__ __forceinline__ void forces_one(const View<R>& v, const Params& P, co
   const V4<R> vpr = v.vp[i];
   const R pw_r = vpr.w;
   const int body_i = ibody(inf);
+  V4<R> udi;
+  if constexpr (TVF) udi = v.ud[i];
   R acc0 = R(0), acc1 = R(0), acc2 = R(0), hs = R(0);
+  R bs0 = R(0), bs1 = R(0), bs2 = R(0);
   bool coincident = false;
   it(false, [&](const Nbr<R>& nb, R d0, R d1, R d2, R r2) {
     if (r2 == R(0)) { coincident = true; return; }
@@ -473,9 +518,22 @@ __device__ __forceinline__ void forces_one(const View<R>& v, const Params& P, co
       const R mB = fj ? nb.rm.y : m_i;
       const R eB = fj ? Mj.eta : eta_i;
       const R uA0 = fluid ? ui.x : vpr.x, uA1 = fluid ? ui.y : vpr.y, uA2 = fluid ? ui.z : vpr.z;
-      R F[3];
+      R F[3], c;
       pair_force<R, DIM>(rA, pA, mA, eA, uA0, uA1, uA2, rB, nb.vp.w, mB, eB, nb.vp.x, nb.vp.y, nb.vp.z, d0, d1, d2,
-                         r, dW, F);
+                         r, dW, F, c);
+      if constexpr (TVF) {
+        if (fluid && fj) pair_stress<R, DIM>(c, rho_i, ui, udi, nb.rm.x, nb.vp.x, nb.vp.y, nb.vp.z, v.ud[nb.j], d0, d1,
+                                             d2, F);
+        if constexpr (IsExact<R>::v) {
+          bs0 = bs0 + c * d0;
+          bs1 = bs1 + c * d1;
+          if (DIM == 3) bs2 = bs2 + c * d2;
+        } else {
+          bs0 = kfma(c, d0, bs0);
+          bs1 = kfma(c, d1, bs1);
+          if (DIM == 3) bs2 = kfma(c, d2, bs2);
+        }
+      }
       acc0 = acc0 + F[0];
       acc1 = acc1 + F[1];
       if (DIM == 3) acc2 = acc2 + F[2];
@@ -520,6 +578,21 @@ __device__ __forceinline__ void forces_one(const View<R>& v, const Params& P, co
     V4<R> av;
     av.x = a0; av.y = a1; av.z = a2; av.w = R(0);
     v.a[i] = av;
+    if constexpr (TVF) {
+      V4<R> b;
+      if constexpr (IsExact<R>::v) {
+        b.x = -(k.pb * bs0) / m_i;
+        b.y = -(k.pb * bs1) / m_i;
+        b.z = DIM == 3 ? -(k.pb * bs2) / m_i : R(0);
+      } else {
+        const R f = -k.pb / m_i;
+        b.x = f * bs0;
+        b.y = f * bs1;
+        b.z = DIM == 3 ? f * bs2 : R(0);
+      }
+      b.w = R(0);
+      v.ab[i] = b;
+    }
     V4<R> un = ui;
     if (kick) {
       un.x = ui.x + k.hdt * a0;
@@ -532,6 +605,12 @@ __device__ __forceinline__ void forces_one(const View<R>& v, const Params& P, co
     f.x = (double)acc0; f.y = (double)acc1; f.z = DIM == 3 ? (double)acc2 : 0.0; f.w = 0.0;
     v.s_f[v.aux[i]] = f;
     v.u_out[i] = ui;
+    if constexpr (TVF) {
+      // a rigid particle that melts starts without a background acceleration
+      V4<R> z;
+      z.x = z.y = z.z = z.w = R(0);
+      v.ab[i] = z;
+    }
   }
   if (coincident) set_err(v.err, ERR_COINCIDENT);
   if (THERMAL) {
@@ -1003,7 +1082,7 @@ __global__ void __launch_bounds__(64) k_extrapolate_list(View<R> v, Params P, KC
 }
 
 // t = (steps begun) x dt, from the scene's device step counter
-template <typename R, int DIM, int THERMAL>
+template <typename R, int DIM, int THERMAL, int TVF>
 __device__ __forceinline__ void forces_wave(const View<R>& v, const Params& P, const KC<R>& k, int w, int kick,
                                             int heat) {
   __shared__ uint32_t jl[Nb<DIM>::rows];
@@ -1027,15 +1106,15 @@ __device__ __forceinline__ void forces_wave(const View<R>& v, const Params& P, c
   const int n_lane = need ? (int)v.nb.cnt[(size_t)w * 64 + lane] : 0;
   const int split = v.nb.split[(size_t)w * 64 + lane];
   const double t = (double)(*v.dstep) * P.dt;
-  forces_one<R, DIM, THERMAL>(v, P, k, smat, i, need, kick, heat, t, [&](bool ws, auto&& f) {
+  forces_one<R, DIM, THERMAL, TVF>(v, P, k, smat, i, need, kick, heat, t, [&](bool ws, auto&& f) {
     for_list<R, DIM, THERMAL == 0>(v, k, smat, g.cx_first, jl, v.nb.ent + (size_t)w * Nb<DIM>::cap * 64 + lane,
                                    n_lane, split, i, T, ws, f);
   });
 }
 
-template <typename R, int DIM, int THERMAL>
+template <typename R, int DIM, int THERMAL, int TVF>
 __global__ void __launch_bounds__(64) k_forces_list(View<R> v, Params P, KC<R> k, int kick, int heat) {
-  forces_wave<R, DIM, THERMAL>(v, P, k, xcd_wave(blockIdx.x, gridDim.x), kick, heat);
+  forces_wave<R, DIM, THERMAL, TVF>(v, P, k, xcd_wave(blockIdx.x, gridDim.x), kick, heat);
 }
 
 // ---------------------------------------------------------------------------
@@ -1074,13 +1153,13 @@ __global__ void __launch_bounds__(64) k_extrapolate_batch(const Slot<R>* tab, in
   extrapolate_wave<R, DIM>(v, P, k, (int)(blockIdx.x - S.b0), (int)S.nb);
 }
 
-template <typename R, int DIM, int THERMAL>
+template <typename R, int DIM, int THERMAL, int TVF>
 __global__ void __launch_bounds__(64) k_forces_batch(const Slot<R>* tab, int ns, int kick, int heat) {
   const Slot<R>& S = tab[find_slot<R>(tab, ns, blockIdx.x)];
   const View<R> v = S.v;
   const Params P = S.P;
   const KC<R> k = S.k;
-  forces_wave<R, DIM, THERMAL>(v, P, k, xcd_wave((int)(blockIdx.x - S.b0), (int)S.nb), kick, heat);
+  forces_wave<R, DIM, THERMAL, TVF>(v, P, k, xcd_wave((int)(blockIdx.x - S.b0), (int)S.nb), kick, heat);
 }
 
 // start of a step: per-evaluation pair counters cleared, step counter advanced
@@ -1154,10 +1233,25 @@ __global__ void __launch_bounds__(256) k_kick_drift(View<R> v, Params P, KC<R> k
     if (P.dim == 3) u.z = u.z + k.hdt * a.z;
     v.u[i] = u;
     if (!isfinite((double)u.x) || !isfinite((double)u.y) || !isfinite((double)u.z)) set_err(v.err, ERR_NONFINITE);
+    // the drift velocity: u^{n+1/2}, or with the transport-velocity
+    // formulation u~^{n+1/2} = u^{n+1/2} + (dt/2) a_b^n
+    V4<R> w = u;
+    if (P.tvf) {
+      const V4<R> b = v.ab[i];
+      V4<R> d;
+      d.x = k.hdt * b.x;
+      d.y = k.hdt * b.y;
+      d.z = P.dim == 3 ? k.hdt * b.z : R(0);
+      d.w = R(0);
+      v.ud[i] = d;
+      w.x = u.x + d.x;
+      w.y = u.y + d.y;
+      if (P.dim == 3) w.z = u.z + d.z;
+    }
     if constexpr (IsExact<R>::v) {
-      x.x = x.x + k.dt * u.x;
-      x.y = x.y + k.dt * u.y;
-      if (P.dim == 3) x.z = x.z + k.dt * u.z;
+      x.x = x.x + k.dt * w.x;
+      x.y = x.y + k.dt * w.y;
+      if (P.dim == 3) x.z = x.z + k.dt * w.z;
       double xx[3] = {x.x, x.y, x.z};
       int c3[3];
       long long lin = cell_of(P, xx, c3);
@@ -1169,7 +1263,7 @@ __global__ void __launch_bounds__(256) k_kick_drift(View<R> v, Params P, KC<R> k
       c3[1] = (int)((c / (uint32_t)P.nc[0]) % (uint32_t)P.nc[1]);
       c3[2] = (int)(c / ((uint32_t)P.nc[0] * (uint32_t)P.nc[1]));
       R o[3] = {x.x, x.y, x.z};
-      const R uu[3] = {u.x, u.y, u.z};
+      const R uu[3] = {w.x, w.y, w.z};
       bool esc = false;
       for (int a = 0; a < P.dim; ++a) {
         o[a] = kfma(k.dt, uu[a], o[a]);
@@ -1441,6 +1535,7 @@ __global__ void __launch_bounds__(256) k_gather(View<R> a, View<R> b, Params P, 
   b.cell[d] = key[s];
   b.u[d] = a.u[s];
   b.a[d] = a.a[s];
+  if (P.tvf) b.ud[d] = a.ud[s];
   b.T[d] = a.T[s];
   b.m[d] = a.m[s];
   b.id[d] = a.id[s];
@@ -1997,16 +2092,20 @@ template <typename R>
 void Launch<R>::forces(const View<R>& v, const Params& P, const KC<R>& k, int kick, int heat, hipStream_t st) {
   if (P.n <= 0) return;
   const unsigned g = (unsigned)P.max_waves;
-  if (P.thermal) {
-    if (P.dim == 2) k_forces_list<R, 2, 1><<<g, 64, 0, st>>>(v, P, k, kick, heat);
-    else k_forces_list<R, 3, 1><<<g, 64, 0, st>>>(v, P, k, kick, heat);
-  } else {
-    if (P.dim == 2) k_forces_list<R, 2, 0><<<g, 64, 0, st>>>(v, P, k, kick, heat);
-    else k_forces_list<R, 3, 0><<<g, 64, 0, st>>>(v, P, k, kick, heat);
+  const int mode = (P.thermal ? 1 : 0) | (P.tvf ? 2 : 0);
+  switch (mode | (P.dim == 3 ? 4 : 0)) {
+    case 0: k_forces_list<R, 2, 0, 0><<<g, 64, 0, st>>>(v, P, k, kick, heat); break;
+    case 1: k_forces_list<R, 2, 1, 0><<<g, 64, 0, st>>>(v, P, k, kick, heat); break;
+    case 2: k_forces_list<R, 2, 0, 1><<<g, 64, 0, st>>>(v, P, k, kick, heat); break;
+    case 3: k_forces_list<R, 2, 1, 1><<<g, 64, 0, st>>>(v, P, k, kick, heat); break;
+    case 4: k_forces_list<R, 3, 0, 0><<<g, 64, 0, st>>>(v, P, k, kick, heat); break;
+    case 5: k_forces_list<R, 3, 1, 0><<<g, 64, 0, st>>>(v, P, k, kick, heat); break;
+    case 6: k_forces_list<R, 3, 0, 1><<<g, 64, 0, st>>>(v, P, k, kick, heat); break;
+    default: k_forces_list<R, 3, 1, 1><<<g, 64, 0, st>>>(v, P, k, kick, heat); break;
   }
 }
 template <typename R>
-void Launch<R>::batch_sweep(int stage, const Slot<R>* tab, int ns, int dim, int thermal, uint32_t blocks, int kick,
+void Launch<R>::batch_sweep(int stage, const Slot<R>* tab, int ns, int dim, int mode, uint32_t blocks, int kick,
                             int heat, hipStream_t st) {
   if (ns <= 0 || blocks == 0) return;
   if (stage == 0) {
@@ -2015,12 +2114,18 @@ void Launch<R>::batch_sweep(int stage, const Slot<R>* tab, int ns, int dim, int 
   } else if (stage == 1) {
     if (dim == 2) k_extrapolate_batch<R, 2><<<blocks, 64, 0, st>>>(tab, ns);
     else k_extrapolate_batch<R, 3><<<blocks, 64, 0, st>>>(tab, ns);
-  } else if (thermal) {
-    if (dim == 2) k_forces_batch<R, 2, 1><<<blocks, 64, 0, st>>>(tab, ns, kick, heat);
-    else k_forces_batch<R, 3, 1><<<blocks, 64, 0, st>>>(tab, ns, kick, heat);
   } else {
-    if (dim == 2) k_forces_batch<R, 2, 0><<<blocks, 64, 0, st>>>(tab, ns, kick, heat);
-    else k_forces_batch<R, 3, 0><<<blocks, 64, 0, st>>>(tab, ns, kick, heat);
+    // mode: bit 0 thermal, bit 1 transport-velocity formulation
+    switch ((mode & 3) | (dim == 3 ? 4 : 0)) {
+      case 0: k_forces_batch<R, 2, 0, 0><<<blocks, 64, 0, st>>>(tab, ns, kick, heat); break;
+      case 1: k_forces_batch<R, 2, 1, 0><<<blocks, 64, 0, st>>>(tab, ns, kick, heat); break;
+      case 2: k_forces_batch<R, 2, 0, 1><<<blocks, 64, 0, st>>>(tab, ns, kick, heat); break;
+      case 3: k_forces_batch<R, 2, 1, 1><<<blocks, 64, 0, st>>>(tab, ns, kick, heat); break;
+      case 4: k_forces_batch<R, 3, 0, 0><<<blocks, 64, 0, st>>>(tab, ns, kick, heat); break;
+      case 5: k_forces_batch<R, 3, 1, 0><<<blocks, 64, 0, st>>>(tab, ns, kick, heat); break;
+      case 6: k_forces_batch<R, 3, 0, 1><<<blocks, 64, 0, st>>>(tab, ns, kick, heat); break;
+      default: k_forces_batch<R, 3, 1, 1><<<blocks, 64, 0, st>>>(tab, ns, kick, heat); break;
+    }
   }
 }
 template <typename R>

@@ -23,9 +23,10 @@ SPH_FP64, SPH_FP32_SWEEP = 0, 1
 SPH_FLUID, SPH_WALL, SPH_RIGID = 0, 1, 2
 SPH_ERR_ESCAPE, SPH_ERR_CELL, SPH_ERR_NONFINITE, SPH_ERR_COINCIDENT, SPH_ERR_BODYCAP = 1, 2, 4, 8, 16
 SPH_BODY_REC = 36
-FIELDS = ["X", "U", "A", "RHO", "P", "T", "PW", "UW", "FR", "M", "DTDT"]
+ABI_VERSION = 2
+FIELDS = ["X", "U", "A", "RHO", "P", "T", "PW", "UW", "FR", "M", "DTDT", "AB", "UD"]
 FIELD_BIT = {f: 1 << k for k, f in enumerate(FIELDS)}
-VEC_FIELDS = {"X", "U", "A", "UW", "FR"}
+VEC_FIELDS = {"X", "U", "A", "UW", "FR", "AB", "UD"}
 
 
 class sph_material(C.Structure):
@@ -56,7 +57,8 @@ class sph_scene_desc(C.Structure):
                 ("wall_A", C.c_double), ("wall_Omega", C.c_double), ("wall_dir", C.c_double * 3),
                 ("heat_src", C.c_int32), ("pad1", C.c_int32),
                 ("src_Q", C.c_double), ("src_sigma", C.c_double), ("src_s0", C.c_double * 2),
-                ("src_v", C.c_double * 2), ("src_ztop", C.c_double), ("src_depth", C.c_double)]
+                ("src_v", C.c_double * 2), ("src_ztop", C.c_double), ("src_depth", C.c_double),
+                ("p_b", C.c_double)]
 
 
 class sph_stats(C.Structure):
@@ -88,6 +90,9 @@ def lib():
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
     L = C.CDLL(LIB_PATH)
     L.sph_abi_version.restype = C.c_int
+    if L.sph_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"{LIB_PATH} has ABI version {L.sph_abi_version()}, this binding needs {ABI_VERSION}: "
+                           "rebuild it with __graft_entry__.build()")
     L.sph_status_string.argtypes = [C.c_int]
     L.sph_status_string.restype = C.c_char_p
     L.sph_last_error.restype = C.c_char_p
@@ -201,6 +206,7 @@ class Desc:
             d.src_s0[a] = sc.src_s0[a]
             d.src_v[a] = sc.src_v[a]
         d.src_ztop, d.src_depth = sc.src_ztop, sc.src_depth
+        d.p_b = getattr(sc, "p_b", 0.0)
         self.desc = d
 
 

@@ -24,11 +24,12 @@ def oracle_fields(o):
     return {
         "X": o.get(O.F_X), "U": o.get(O.F_U), "A": o.get(O.F_A), "RHO": o.get(O.F_RHO), "P": o.get(O.F_P),
         "T": o.get(O.F_T), "PW": o.get(O.F_PW), "UW": o.get(O.F_UW), "FR": o.get(O.F_FR),
+        "AB": o.get(O.F_AB), "UD": o.get(O.F_UD),
     }
 
 
 def gpu_fields(g):
-    return g.sph_scene_read_particles(["X", "U", "A", "RHO", "P", "T", "PW", "UW", "FR"])
+    return g.sph_scene_read_particles(["X", "U", "A", "RHO", "P", "T", "PW", "UW", "FR", "AB", "UD"])
 
 
 def field_errors(sc, gf, of, kind):
@@ -51,6 +52,11 @@ def field_errors(sc, gf, of, kind):
         out["fr"] = np.max(np.abs(gf["FR"][rg] - of["FR"][rg])) / f_scale
     if sc.thermal:
         out["T"] = np.max(np.abs(gf["T"] - of["T"])) / s["T"]
+    if getattr(sc, "p_b", 0.0) > 0.0 and fl.any():
+        # transport-velocity formulation: a_b against the size of one pair
+        # term, p_b / (rho0 dx); u~ - u against the velocity scale
+        out["ab"] = np.max(np.abs(gf["AB"][fl] - of["AB"][fl])) / (sc.p_b / (s["rho"] * sc.dx))
+        out["ud"] = np.max(np.abs(gf["UD"][fl] - of["UD"][fl])) / s["u"]
     return out
 
 

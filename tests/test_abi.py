@@ -22,7 +22,7 @@ def test_exports_every_header_symbol(L):
 
 
 def test_version_and_status(L):
-    assert B.sph_abi_version() == 1
+    assert B.sph_abi_version() == 2
     assert B.sph_status_string(B.SPH_E_INVALID) == "invalid argument"
 
 

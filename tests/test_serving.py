@@ -117,10 +117,16 @@ def _mix_requests(B):
         Request(2, th, 10, 0.0, B.SPH_FP32_SWEEP),
         Request(3, _scripted_switch_scene(), 10, 0.005, B.SPH_FP64),
         Request(4, small_3d(seed=7), 7, 0.01, B.SPH_FP64),
+        Request(5, _tvf(small_3d(seed=8)), 8, 0.0, B.SPH_FP32_SWEEP),
     ]
 
 
-FIELDS = ["X", "U", "A", "RHO", "P", "T", "PW", "UW", "FR"]
+def _tvf(sc):
+    sc.p_b = sc.materials[0].p0
+    return sc
+
+
+FIELDS = ["X", "U", "A", "RHO", "P", "T", "PW", "UW", "FR", "AB", "UD"]
 
 
 @pytest.mark.gpu
