@@ -280,8 +280,16 @@ def main():
     }
 
     if args.other_steps > 0:
-        c3 = S.config_c3(seed=args.seed)
+        tv = S.config_c2(seed=args.seed)
+        tv.p_b = tv.materials[0].p0
         out["other_workloads"] = [
+            timed_workload(B, tv, args.other_steps,
+                           "the same 3D column with the transport-velocity formulation on (background pressure "
+                           "p_b = p0, as in the paper's examples)"),
+        ]
+        del tv
+        c3 = S.config_c3(seed=args.seed)
+        out["other_workloads"] += [
             timed_workload(B, c3, args.other_steps,
                            "two-phase thermal grains with conduction, moving heat source and phase switching, "
                            "200x200x100 fluid sites, 2000 grains requested (log-normal radii, median 4.3 dx)"),

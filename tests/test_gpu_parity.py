@@ -250,13 +250,16 @@ def test_phase_switch_body_capacity_error(B):
 
 # ---- checkpoint / resume ----------------------------------------------------
 
-@pytest.mark.parametrize("case", ["c1_fp64", "switch_fp64", "3d_fp32"])
+@pytest.mark.parametrize("case", ["c1_fp64", "switch_fp64", "3d_fp32", "3d_tvf_fp32"])
 def test_checkpoint_resume_is_bitwise(B, case):
     """k steps, state image, re-create, N-k steps == N steps, bit for bit."""
     if case == "c1_fp64":
         sc, prec = S.config_c1(seed=2), B.SPH_FP64
     elif case == "switch_fp64":
         sc, prec = _scripted_switch_scene(), B.SPH_FP64
+    elif case == "3d_tvf_fp32":
+        sc, prec = small_3d(seed=4), B.SPH_FP32_SWEEP
+        sc.p_b = sc.materials[0].p0
     else:
         sc, prec = small_3d(seed=3), B.SPH_FP32_SWEEP
     k, n = 7, 19
