@@ -948,10 +948,15 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
         }
         msk[wd * 64 + lane] = m;
       }
-      // the hits in candidate order: density, and into the lane's list
-      for (int wd = 0; wd < nwd; ++wd) {
-        uint32_t m = msk[wd * 64 + lane];
-        while (m != 0u) {
+      // the hits in candidate order: density, and into the lane's list.
+      // Every lane walks its own hits across all words of the segment, so
+      // the wave loops max-over-lanes of the segment's hits (not the sum
+      // over words of each word's maximum)
+      int wd = 0;
+      uint32_t m = nwd > 0 ? msk[lane] : 0u;
+      while (m == 0u && wd + 1 < nwd) m = msk[++wd * 64 + lane];
+      while (m != 0u) {
+        {
           const int bit = __builtin_clz(m);
           m &= ~(0x80000000u >> bit);
           const int q = qs + 32 * wd + bit;
@@ -969,6 +974,7 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
           nf += (room && front) ? 1 : 0;
           nb += (room && !front) ? 1 : 0;
         }
+        while (m == 0u && wd + 1 < nwd) m = msk[++wd * 64 + lane];
       }
       __syncthreads();
     }
