@@ -67,7 +67,12 @@ enum {
  * the body force per unit mass; T_t the transition temperature and
  * switch_to the partner phase of a melting / solidification
  * (Sec. "Modeling thermally driven reversible phase transitions"), -1 for
- * none; dirichlet marks wall phases whose temperature is prescribed. */
+ * none; dirichlet marks phases whose scalar is prescribed: walls of such a
+ * phase take part in conduction (V = dx^d, the phase's kappa), fluid and
+ * rigid particles of such a phase keep their value.  The same scalar solver
+ * carries a concentration C (the remark on concentration-driven transitions
+ * in Sec. "Reversible phase transition"): cp = 1, kappa = D, T = C and
+ * T_t = C_t. */
 typedef struct {
   double rho0, p0, nu, cp, kappa;
   double b[3];

@@ -588,7 +588,10 @@ static double heat_source(const orc_scene *s, int64_t a, double t) {
  * particles a, c_p,a dT_a/dt = 1/rho_a sum_b V_b 4 k_a k_b/(k_a + k_b)
  * T_ab / r_ab dW/dr, all rates from T^n; then T^{n+1} = T^n + dt dT/dt.
  * Walls take part as neighbours only where their temperature is
- * prescribed, with V_b = dx^d. */
+ * prescribed, with V_b = dx^d and their phase's conductivity.  With
+ * c_p = 1 and k = D the same operator is the diffusion equation of a
+ * concentration (the remark on concentration-driven transitions in Sec.
+ * "Reversible phase transition"): C in place of T, transitions at C_t. */
 static int stage_heat(orc_scene *s, int update) {
   double t = s->t;
   for (int64_t a = 0; a < s->n; ++a) {
@@ -618,9 +621,12 @@ static int stage_heat(orc_scene *s, int update) {
     if (s->heat_src) rate = rate + heat_source(s, a, t) / Ma->cp;
     s->dTdt[a] = rate;
   }
+  /* a fluid or rigid phase with a prescribed value keeps it (the gastric
+   * juice of Sec. "Gastric disintegration of food boluses" holds its
+   * concentration at all times) */
   if (update)
     for (int64_t a = 0; a < s->n; ++a)
-      if (s->kind[a] != ORC_WALL) s->T[a] = s->T[a] + s->dt * s->dTdt[a];
+      if (s->kind[a] != ORC_WALL && !s->mat[s->phase[a]].dirichlet) s->T[a] = s->T[a] + s->dt * s->dTdt[a];
   return ORC_OK;
 }
 

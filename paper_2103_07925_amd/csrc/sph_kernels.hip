@@ -625,7 +625,8 @@ __device__ __forceinline__ void forces_one(const View<R>& v, const Params& P, co
       else rate = kfma(heat_source<R>(P, t, x), Mi.inv_cp, rate);
     }
     v.dTdt[i] = rate;
-    v.T_out[i] = heat ? Ti + k.dt * rate : Ti;
+    // a phase with a prescribed value (e.g. a fixed concentration) keeps it
+    v.T_out[i] = (heat && Li.dir == R(0)) ? Ti + k.dt * rate : Ti;
   }
 }
 

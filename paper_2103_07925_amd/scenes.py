@@ -431,6 +431,81 @@ def config_c4(seed: int = 0, nsites=(400, 200, 100), dx: float = 0.1, n_frag: in
     return sc
 
 
+def config_gastric(seed: int = 0, dx: float = 0.1, size=(40.0, 16.0), n_bolus: int = 60,
+                   d_range=(1.6, 2.8), c: float = 1.0e3, C_t: float = 0.8, pb_factor: float = 5.0,
+                   opening: float = 0.5, amplitude: float = 14.5, period: float = 2.0) -> Scene:
+    """2D box (size[0] x size[1], 3 wall layers) with a moving constriction
+    and rigid food boluses dissolving by a concentration, shaped like the
+    gastric example (Sec. "Gastric disintegration of food boluses"):
+    boluses (rigid discs of diameters U(d_range), density 1, D = 0.25,
+    C = 0, dissolving into chyme above C_t) placed by random sequential
+    addition; gastric juice (fluid, density 1, nu = 100, D = 1, C held at 1);
+    chyme (fluid, nu = 200, D = 0.25, no further transition); no-flux walls.
+    The constriction is a 3-layer wall plate normal to x with a central
+    opening of `opening` x height, starting at x = size[0]/2 + amplitude and
+    moving by amplitude (cos(2 pi t / period) - 1).  The concentration is
+    carried by the scalar solver (cp = 1, kappa = D); the transport-velocity
+    formulation is on with p_b = pb_factor p0."""
+    dim = 2
+    rng = np.random.default_rng(seed)
+    nsites = (int(round(size[0] / dx)), int(round(size[1] / dx)))
+    inner, walls, lo, hi = box_and_walls(dim, nsites, dx)
+    ext = np.array([nsites[0] * dx, nsites[1] * dx])
+    p0 = 1.0 * c * c
+    mats = [
+        Material(rho0=1.0, cp=1.0, kappa=0.25, T_t=C_t, switch_to=2),                    # 0 bolus (solid)
+        Material(rho0=1.0, p0=p0, nu=100.0, cp=1.0, kappa=1.0, dirichlet=1),              # 1 gastric juice
+        Material(rho0=1.0, p0=p0, nu=200.0, cp=1.0, kappa=0.25, T_t=C_t),                 # 2 chyme
+        Material(rho0=1.0),                                                              # 3 wall (no flux)
+    ]
+    kind_of = np.full(inner.shape[0], FLUID, np.int32)
+    phase_of = np.full(inner.shape[0], 1, np.int32)
+    body_of = np.full(inner.shape[0], -1, np.int32)
+    x0 = 0.5 * ext[0] + amplitude
+    plate = np.abs(inner[:, 0] - x0) < 1.5 * dx
+    plate &= ~(np.abs(inner[:, 1] - 0.5 * ext[1]) < 0.5 * opening * ext[1])
+    kind_of[plate] = WALL
+    phase_of[plate] = 3
+    radii = np.sort(0.5 * rng.uniform(d_range[0], d_range[1], n_bolus))[::-1]
+    placed = np.zeros((n_bolus, 2))
+    placed_r = np.zeros(n_bolus)
+    k = 0
+    bodies = []
+    for R in radii:
+        for _ in range(500):
+            cpos = np.array([rng.uniform(R + 2 * dx, ext[0] - R - 2 * dx), rng.uniform(R + 2 * dx, ext[1] - R - 2 * dx)])
+            if abs(cpos[0] - x0) < R + 4 * dx:
+                continue
+            if np.any(np.sum((placed[:k] - cpos) ** 2, axis=1) < (placed_r[:k] + R + dx) ** 2):
+                continue
+            idx = ball_sites(nsites, dx, dim, np.array([cpos[0], cpos[1], 0.0]), R)
+            idx = idx[kind_of[idx] == FLUID]
+            if idx.size < 4:
+                break
+            placed[k] = cpos
+            placed_r[k] = R
+            k += 1
+            kind_of[idx] = RIGID
+            phase_of[idx] = 0
+            body_of[idx] = len(bodies)
+            bodies.append(BodyInit())
+            break
+    C = np.where(kind_of == RIGID, 0.0, 1.0)
+    groups = [
+        (inner[kind_of == FLUID], FLUID, 1, -1, 0, C[kind_of == FLUID]),
+        (inner[kind_of == RIGID], RIGID, 0, body_of[kind_of == RIGID], 0, C[kind_of == RIGID]),
+        (walls, WALL, 3, -1, 0, 0.0),
+        (inner[kind_of == WALL], WALL, 3, -1, 1, 0.0),
+    ]
+    sc = _assemble("gastric", dim, dx, lo, hi, groups, mats, bodies, max_bodies=len(bodies),
+                   thermal=1, phase_switch=1, wall_A=amplitude, wall_Omega=2.0 * math.pi / period,
+                   wall_dir=(1.0, 0.0, 0.0))
+    sc.x = jitter(sc.x, sc.kind == FLUID, dx, rng, dim)
+    sc.p_b = pb_factor * p0
+    sc.meta.update(seed=seed, c=c)
+    return sc
+
+
 def config_e7(dx: float = 0.2) -> Scene:
     """Strong-scaling scene of Sec. "Strong scaling analysis": cubic box
     L = 30, 216 spheres D = 2.5 (density 10) on a regular grid with centres

@@ -135,6 +135,22 @@ def test_fp32_gates(B, make):
     assert eb["r"] <= 1e-3 and eb["m"] <= 1e-12, eb
 
 
+@pytest.mark.parametrize("p_b", [0.0, 1.0])
+def test_fp32_full_run_gates(B, p_b):
+    """The C1 run's full 1000 steps in the FP32 sweep (with and without the
+    transport-velocity formulation): positions and velocities within 1e-3,
+    densities and every body error within 1e-4 (gates fixed before
+    measuring)."""
+    sc = S.config_c1(seed=0)
+    sc.p_b = p_b * sc.materials[0].p0
+    o, g = run_pair(sc, B.SPH_FP32_SWEEP, 1000)
+    e = field_errors(sc, gpu_fields(g), oracle_fields(o), o.get_int(O.I_KIND))
+    assert e["x"] <= 1e-3 and e["u"] <= 1e-3, e
+    assert e["rho"] <= 1e-4 and e["p"] <= 1e-4, e
+    eb = body_errors(sc, g.bodies(), o.bodies())
+    assert max(eb.values()) <= 1e-4, eb
+
+
 # ---- reversible phase transition -------------------------------------------
 
 def _scripted_switch_scene():
