@@ -288,6 +288,12 @@ def main():
                            "p_b = p0, as in the paper's examples)"),
         ]
         del tv
+        gs = S.config_gastric(seed=args.seed)
+        out["other_workloads"].append(
+            timed_workload(B, gs, args.other_steps,
+                           "2D gastric-shaped box 40 x 16 (dx 0.1): moving constriction, 60 boluses dissolving "
+                           "into chyme by concentration, juice held at C = 1, p_b = 5 p0"))
+        del gs
         c3 = S.config_c3(seed=args.seed)
         out["other_workloads"] += [
             timed_workload(B, c3, args.other_steps,
