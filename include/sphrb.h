@@ -101,10 +101,11 @@ typedef struct {
   int64_t n;                   /* particles */
   const double *x, *u, *T;     /* [n][3], [n][3], [n] (T may be NULL) */
   const int32_t *kind;         /* SPH_FLUID / SPH_WALL / SPH_RIGID */
-  const int32_t *phase;        /* material index, < 256 */
+  const int32_t *phase;        /* material index, < n_mat */
   const int32_t *body;         /* body index of rigid particles, else ignored */
   const int32_t *moving;       /* walls following the wall motion (may be NULL) */
-  int32_t n_mat, n_body;
+  int32_t n_mat, n_body;       /* 1..256 materials; fluid phases, switch targets and every
+                                  phase of a thermal scene among the first 16 */
   const sph_material *mat;
   const sph_body_init *bodies;
   int32_t max_bodies;          /* capacity for bodies created by solidification */

@@ -157,6 +157,12 @@ int validate(const sph_scene_desc* d) {
   if (d->n < 0 || d->n > 0x7fffffffLL) return fail(SPH_E_INVALID, "particle count out of range");
   if (d->n > 0 && (!d->x || !d->u || !d->kind || !d->phase)) return fail(SPH_E_INVALID, "missing particle arrays");
   if (d->n_mat <= 0 || d->n_mat > 256 || !d->mat) return fail(SPH_E_INVALID, "1..256 materials required");
+  if (d->thermal && d->n_mat > kLdsPhases)
+    return fail(SPH_E_UNSUPPORTED, "a thermal scene has at most " + std::to_string(kLdsPhases) + " materials");
+  for (int k = 0; k < d->n_mat; ++k)
+    if (d->mat[k].switch_to >= kLdsPhases && d->phase_switch)
+      return fail(SPH_E_UNSUPPORTED, "switch targets must be among the first " + std::to_string(kLdsPhases) +
+                                         " materials");
   if (d->n_body < 0 || (d->n_body > 0 && !d->bodies)) return fail(SPH_E_INVALID, "bad bodies");
   if (std::max(d->max_bodies, d->n_body) > 65534) return fail(SPH_E_INVALID, "too many bodies");
   double rc = 3.0 * d->dx;
@@ -173,6 +179,9 @@ int validate(const sph_scene_desc* d) {
     int k = d->kind[i];
     if (k < 0 || k > 2) return fail(SPH_E_INVALID, "bad kind at " + std::to_string(i));
     if (d->phase[i] < 0 || d->phase[i] >= d->n_mat) return fail(SPH_E_INVALID, "bad phase at " + std::to_string(i));
+    if (d->kind[i] == SPH_FLUID && d->phase[i] >= kLdsPhases)
+      return fail(SPH_E_UNSUPPORTED, "fluid phases must be among the first " + std::to_string(kLdsPhases) +
+                                         " materials (particle " + std::to_string(i) + ")");
     if (k == SPH_RIGID && (!d->body || d->body[i] < 0 || d->body[i] >= d->n_body))
       return fail(SPH_E_INVALID, "bad body at " + std::to_string(i));
     if (k == SPH_FLUID && d->mat[d->phase[i]].p0 <= 0.0)

@@ -15,6 +15,12 @@
 
 namespace sphrb {
 
+// The sweeps keep the constants of the first kLdsPhases phases in LDS.
+// Fluid phases (and the fluid phases a switch can produce) must be among
+// them, and every phase of a thermal scene; rigid and wall particles of
+// later phases carry their density and mass in their neighbour record.
+constexpr int kLdsPhases = 16;
+
 // Pair counters: kPairSlots counters ([0] last evaluation, [1] running
 // total, [2] fluid targets, [3] fluid neighbours of rigid targets, [4] fluid
 // neighbours of walls), each spread over kPairParts partial sums kPairStride

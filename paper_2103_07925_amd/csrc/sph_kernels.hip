@@ -237,8 +237,13 @@ __device__ __forceinline__ uint32_t r_to_info(float v) { return __float_as_uint(
 __device__ __forceinline__ uint32_t r_to_info(double v) { return (uint32_t)v; }
 
 // Per-phase constants the sweeps need for every neighbour, kept in LDS for
-// the first kMatLds phases (the rest are read from the global table).
-constexpr int kMatLds = 16;
+// the first kLdsPhases phases.  Set-up guarantees that the sweeps only ask
+// for those (fluid phases, every phase of a thermal scene; a rigid or wall
+// neighbour of a later phase brings its density and mass in its record), so
+// a lookup is one LDS read: a fallback to the global table would become a
+// flat load, which waits for every outstanding global load of the wave and
+// defeats the pipelined list walks.
+constexpr int kMatLds = kLdsPhases;
 template <typename R>
 struct MatL {
   R eta, kappa, rho0, p0, inv_p0, b0, b1, b2, dir, mass;
@@ -259,9 +264,8 @@ __device__ __forceinline__ void stage_mats(MatL<R>* sm, const View<R>& v, const 
   __syncthreads();
 }
 template <typename R>
-__device__ __forceinline__ MatL<R> mat_of(const MatL<R>* sm, const View<R>& v, uint32_t ph) {
-  if (ph < (uint32_t)kMatLds) return sm[ph];
-  return mat_from<R>(v.mat[ph]);
+__device__ __forceinline__ MatL<R> mat_of(const MatL<R>* sm, const View<R>&, uint32_t ph) {
+  return sm[ph < (uint32_t)kMatLds ? ph : 0u];   // clamped: a later phase's result is never used
 }
 
 // wall / rigid extrapolation (local force balance of Adami et al. 2012):
@@ -744,10 +748,23 @@ struct NbRec {
 // gl: the lane's column of its wave's list block; jl: the stencil-row bases
 // of the lane's wave; cx_first: the first cell of the lane's wave (frame)
 // (entries q0, q0 + dq, ... of the first n_lane)
+// frame offsets (dy L, dz L) of the stencil rows of the list walks, into LDS
+// (rows in the order dz outer, dy inner; 2D: dz = 0); the caller synchronises
+template <typename R, int DIM>
+__device__ __forceinline__ void stage_rows(R* ro, const KC<R>& k) {
+  constexpr int NR = Nb<DIM>::rows;
+  const int t = (int)threadIdx.x;
+  if (t < NR) {
+    ro[2 * t] = (R)(t % 3 - 1) * k.L;
+    ro[2 * t + 1] = DIM == 3 ? (R)(t / 3 - 1) * k.L : R(0);
+  }
+}
+
 template <typename R, int DIM, bool PACKED, typename F>
-__device__ __forceinline__ void for_list(const View<R>& v, const KC<R>& k, const MatL<R>* sm, int cx_first,
-                                         const uint32_t* jl, const uint16_t* gl, int n_all, int split, uint32_t i,
-                                         const V4<R>& T, bool with_self, F&& visit, int q0 = 0, int dq = 1) {
+__device__ __forceinline__ void for_list(const View<R>& v, const KC<R>& k, const MatL<R>* sm, const R* ro,
+                                         int cx_first, const uint32_t* jl, const uint16_t* gl, int n_all, int split,
+                                         uint32_t i, const V4<R>& T, bool with_self, F&& visit, int q0 = 0,
+                                         int dq = 1) {
   constexpr int CAP = Nb<DIM>::cap;
   constexpr bool PK = PACKED && !IsExact<R>::v;
   const int n_lane = n_all > q0 ? (n_all - q0 + dq - 1) / dq : 0;   // this lane's entries
@@ -786,7 +803,6 @@ __device__ __forceinline__ void for_list(const View<R>& v, const KC<R>& k, const
       const uint32_t rr = e0 >> 12;
       const uint32_t j = index(e0);
       if (j != i || with_self) {
-        const int dz = DIM == 3 ? (int)(rr / 3u) - 1 : 0, dy = (int)(rr % 3u) - 1;
         Nbr<R> nb;
         nb.j = j;
         nb.vp = r0.vp;
@@ -811,7 +827,17 @@ __device__ __forceinline__ void for_list(const View<R>& v, const KC<R>& k, const
           pj = r0.a;
           nb.rm = r0.rm;
         }
-        const V4<R> sj = to_frame<R>(pj, k, cx_first, dy, dz);
+        V4<R> sj;
+        if constexpr (IsExact<R>::v) {
+          sj = pj;
+        } else {
+          // the wave's frame (cf. to_frame): dy L and dz L are exact, so the
+          // sums round like the fused forms
+          sj.x = kfma(pj.w - (R)cx_first, k.L, pj.x);
+          sj.y = pj.y + ro[2 * rr];
+          sj.z = pj.z + ro[2 * rr + 1];
+          sj.w = R(0);
+        }
         R d0, d1, d2;
         const R r2 = dist2<R, DIM>(T, sj, d0, d1, d2);
         visit(nb, d0, d1, d2, r2);
@@ -1017,7 +1043,7 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
     if constexpr (!IsExact<R>::v) {
       const V4<R> po = v.pos[i];
       const uint32_t pk = (uint32_t)po.w | (kind << 16) | (iphase(inf) << 18) |
-                          ((v.m[i] != M.mass ? 1u : 0u) << 26);
+                          ((v.m[i] != M.mass || iphase(inf) >= (uint32_t)kMatLds ? 1u : 0u) << 26);
       V4<R> pa;
       pa.x = po.x;
       pa.y = po.y;
@@ -1056,6 +1082,8 @@ __device__ __forceinline__ void extrapolate_wave(const View<R>& v, const Params&
   const uint32_t total = *v.nb.ext_n;
   if ((uint32_t)blk * kExtPerBlock >= total) return;
   __shared__ MatL<R> smat[kMatLds];
+  __shared__ R ro[2 * NR];
+  stage_rows<R, DIM>(ro, k);
   stage_mats<R>(smat, v, P);
   const int lane = threadIdx.x, sub = lane & (kExtSub - 1);
   for (uint32_t b = (uint32_t)blk; b * kExtPerBlock < total; b += (uint32_t)nblk) {
@@ -1073,7 +1101,7 @@ __device__ __forceinline__ void extrapolate_wave(const View<R>& v, const Params&
     const int n_f = need ? (int)v.nb.split[(size_t)w * 64 + l] : 0;
     unsigned long long cr = 0, cw = 0;
     const uint32_t c = extrap_one<R, DIM, kExtSub>(v, k, smat, i, need, sub == 0, [&](bool ws, auto&& f) {
-      for_list<R, DIM, true>(v, k, smat, g.cx_first, jls + lane * NR, v.nb.ent + (size_t)w * CAP * 64 + l, n_f,
+      for_list<R, DIM, true>(v, k, smat, ro, g.cx_first, jls + lane * NR, v.nb.ent + (size_t)w * CAP * 64 + l, n_f,
                              n_f, i, T, ws, f, sub, kExtSub);
     });
     if (need && sub == 0 && kind == KR) cr = c;
@@ -1107,6 +1135,8 @@ __device__ __forceinline__ void forces_wave(const View<R>& v, const Params& P, c
   const bool need = active && kind != KW;
   if (!__any(need)) return;
   __shared__ MatL<R> smat[kMatLds];
+  __shared__ R ro[2 * Nb<DIM>::rows];
+  stage_rows<R, DIM>(ro, k);
   stage_mats<R>(smat, v, P);
   stage_jlo<DIM>(jl, v.nb, w);
   const V4<R> T = to_frame<R>(v.pos[i], k, g.cx_first, 0, 0);
@@ -1114,7 +1144,7 @@ __device__ __forceinline__ void forces_wave(const View<R>& v, const Params& P, c
   const int split = v.nb.split[(size_t)w * 64 + lane];
   const double t = (double)(*v.dstep) * P.dt;
   forces_one<R, DIM, THERMAL, TVF>(v, P, k, smat, i, need, kick, heat, t, [&](bool ws, auto&& f) {
-    for_list<R, DIM, THERMAL == 0>(v, k, smat, g.cx_first, jl, v.nb.ent + (size_t)w * Nb<DIM>::cap * 64 + lane,
+    for_list<R, DIM, THERMAL == 0>(v, k, smat, ro, g.cx_first, jl, v.nb.ent + (size_t)w * Nb<DIM>::cap * 64 + lane,
                                    n_lane, split, i, T, ws, f);
   });
 }
