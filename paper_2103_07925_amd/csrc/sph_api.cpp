@@ -157,6 +157,8 @@ int validate(const sph_scene_desc* d) {
   if (d->n < 0 || d->n > 0x7fffffffLL) return fail(SPH_E_INVALID, "particle count out of range");
   if (d->n > 0 && (!d->x || !d->u || !d->kind || !d->phase)) return fail(SPH_E_INVALID, "missing particle arrays");
   if (d->n_mat <= 0 || d->n_mat > 256 || !d->mat) return fail(SPH_E_INVALID, "1..256 materials required");
+  if (d->phase_switch && !d->thermal)
+    return fail(SPH_E_INVALID, "phase switching needs the scalar (thermal) solver");
   if (d->thermal && d->n_mat > kLdsPhases)
     return fail(SPH_E_UNSUPPORTED, "a thermal scene has at most " + std::to_string(kLdsPhases) + " materials");
   for (int k = 0; k < d->n_mat; ++k)

@@ -166,8 +166,8 @@ struct View {
   V4<R>* ab;   // transport-velocity formulation: background-pressure acceleration
   V4<R>* vp;   // neighbour record: (u, p) of fluid, (u~_w, p_w) of wall / rigid particles
   V4<R>* rm;   // neighbour record: (rho, m, info bits, T)
-  V4<R>* pa;   // FP32 neighbour record: cell offsets x, y, z and packed cell x /
-               // kind / phase / mass-not-of-phase bits (see pack_pa)
+  V4<R>* pa;   // FP32 neighbour record: cell offsets x, y, z and packed
+               // cell x | kind << 16 | phase << 18
   // cells
   uint32_t* cstart;   // C + 1
   // rigid slots (body-sorted)

@@ -813,16 +813,17 @@ __device__ __forceinline__ void for_list(const View<R>& v, const KC<R>& k, const
           pj.y = r0.a.y;
           pj.z = r0.a.z;
           pj.w = (R)(pk & 0xffffu);
-          if ((pk >> 26) & 1u) {
-            nb.rm = v.rm[j];
-          } else {
-            const uint32_t kj = (pk >> 16) & 3u, ph = (pk >> 18) & 0xffu;
-            const MatL<R> M = mat_of<R>(sm, v, ph);
-            nb.rm.x = kj == KF ? inv_eos<R>(M, nb.vp.w) : M.rho0;
-            nb.rm.y = M.mass;
-            nb.rm.z = info_to_r(mkinfo(kj, ph, 0u, -1), R(0));
-            nb.rm.w = R(0);
-          }
+          // density and mass from the phase: a fluid neighbour has its
+          // phase's mass (only melting, which needs the scalar solver and so
+          // the unpacked walk, makes a fluid particle with another mass); a
+          // wall or rigid neighbour's density and mass are not used by the
+          // walks that take packed records
+          const uint32_t kj = (pk >> 16) & 3u, ph = (pk >> 18) & 0xffu;
+          const MatL<R> M = mat_of<R>(sm, v, ph);
+          nb.rm.x = kj == KF ? inv_eos<R>(M, nb.vp.w) : M.rho0;
+          nb.rm.y = M.mass;
+          nb.rm.z = info_to_r(mkinfo(kj, ph, 0u, -1), R(0));
+          nb.rm.w = R(0);
         } else {
           pj = r0.a;
           nb.rm = r0.rm;
@@ -1042,8 +1043,7 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
     v.rho[i] = rho;
     if constexpr (!IsExact<R>::v) {
       const V4<R> po = v.pos[i];
-      const uint32_t pk = (uint32_t)po.w | (kind << 16) | (iphase(inf) << 18) |
-                          ((v.m[i] != M.mass || iphase(inf) >= (uint32_t)kMatLds ? 1u : 0u) << 26);
+      const uint32_t pk = (uint32_t)po.w | (kind << 16) | (iphase(inf) << 18);
       V4<R> pa;
       pa.x = po.x;
       pa.y = po.y;
