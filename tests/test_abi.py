@@ -54,6 +54,43 @@ def test_invalid_descriptors_rejected(mutate, what):
     assert what in B.sph_last_error()
 
 
+def _many_phases(sc, n, fluid_phase=None, thermal=0):
+    """sc with n materials; optionally its fluid particles moved to fluid_phase."""
+    extra = [S.Material(rho0=sc.materials[0].rho0, p0=sc.materials[0].p0, nu=sc.materials[0].nu)
+             for _ in range(n - len(sc.materials))]
+    sc.materials = list(sc.materials) + extra
+    if fluid_phase is not None:
+        sc.phase[sc.kind == S.FLUID] = fluid_phase
+    sc.thermal = thermal
+    return sc
+
+
+@pytest.mark.parametrize("mutate,status,what", [
+    (lambda sc: _many_phases(sc, 20, fluid_phase=17), "UNSUPPORTED", "fluid phases"),
+    (lambda sc: _many_phases(sc, 20, thermal=1), "UNSUPPORTED", "thermal scene"),
+    (lambda sc: setattr(sc, "phase_switch", 1), "INVALID", "scalar (thermal) solver"),
+    (lambda sc: setattr(sc, "p_b", -1.0), "INVALID", "background pressure"),
+])
+def test_scene_limits_rejected(mutate, status, what):
+    """The sweeps' LDS phase table, phase switching and the transport-velocity
+    option have set-up conditions; a descriptor that breaks one is refused
+    before any device call."""
+    sc = S.config_c1()
+    mutate(sc)
+    with pytest.raises(B.SphError) as e:
+        B.sph_scene_arena_bytes(B.Desc(sc, B.SPH_FP32_SWEEP))
+    assert e.value.status == getattr(B, "SPH_E_" + status)
+    assert what in B.sph_last_error()
+
+
+def test_many_rigid_phases_accepted():
+    """Rigid phases beyond the first 16 materials are fine (the 3D column
+    gives every sphere its own density)."""
+    sc = S.config_c2(seed=0, n_side=24, n_per_axis=3, spacing_sites=8, r_range=(2.0, 3.0))
+    assert len(sc.materials) > 16
+    assert B.sph_scene_arena_bytes(B.Desc(sc, B.SPH_FP32_SWEEP)) > 0
+
+
 @pytest.mark.parametrize("blob", [b"", b"not a state image at all" * 4, b"SPHRBST1" + b"\0" * 64])
 def test_state_images_rejected(blob):
     """A buffer that is not a whole state image is refused before any device call."""
