@@ -591,10 +591,15 @@ size_t slot_bytes(int precision) { return precision == SPH_FP64 ? sizeof(Slot<do
 constexpr size_t kSlotMax = sizeof(Slot<double>) > sizeof(Slot<float>) ? sizeof(Slot<double>) : sizeof(Slot<float>);
 
 template <typename R>
-void fill_slot(sph_scene* s, uint32_t b0, uint32_t nb, char* dst) {
+void fill_slot(sph_scene* s, uint32_t b0, uint32_t nb, const char* gbase, char* dst) {
   Slot<R> sl;
   std::memset(&sl, 0, sizeof(sl));
   sl.v = cur<R>(s);
+  // pointers as offsets from the batch's global base (see for_each_ptr)
+  for_each_ptr(sl.v, [&](auto*& p) {
+    using T = std::remove_reference_t<decltype(*p)>;
+    p = reinterpret_cast<T*>(reinterpret_cast<intptr_t>(p) - reinterpret_cast<intptr_t>(gbase));
+  });
   sl.P = s->P;
   sl.k = make_kc<R>(s->P);
   sl.b0 = b0;
@@ -630,8 +635,8 @@ int group_table(sph_batch* b, sph_batch::Group& g, int* which_out) {
   for (size_t q = 0; q < g.members.size(); ++q) {
     sph_scene* s = b->scenes[g.members[q]];
     const uint32_t nb = (uint32_t)((s->P.max_waves + 7) / 8 * 8);
-    if (g.precision == SPH_FP64) fill_slot<double>(s, b0, nb, &g.host[which][q * sb]);
-    else fill_slot<float>(s, b0, nb, &g.host[which][q * sb]);
+    if (g.precision == SPH_FP64) fill_slot<double>(s, b0, nb, b->ws, &g.host[which][q * sb]);
+    else fill_slot<float>(s, b0, nb, b->ws, &g.host[which][q * sb]);
     b0 += nb;
   }
   g.blocks = b0;
@@ -643,8 +648,8 @@ int group_table(sph_batch* b, sph_batch::Group& g, int* which_out) {
 
 template <typename R>
 void group_sweep(sph_batch* b, sph_batch::Group& g, int which, int stage) {
-  Launch<R>::batch_sweep(stage, reinterpret_cast<const Slot<R>*>(b->ws + g.off[which]), (int)g.members.size(),
-                         g.dim, g.mode, g.blocks, 1, 1, b->stream);
+  Launch<R>::batch_sweep(stage, reinterpret_cast<const Slot<R>*>(b->ws + g.off[which]), b->ws,
+                         (int)g.members.size(), g.dim, g.mode, g.blocks, 1, 1, b->stream);
 }
 
 // the host-side bookkeeping of one step, without its launches (a replayed

@@ -205,6 +205,25 @@ struct Slot {
   uint32_t b0, nb;   // first block in the batched grid and block count (multiples of 8)
 };
 
+// Every buffer pointer of a view, for rebasing the views of a batched slot
+// table: the host stores each pointer as an offset from one global base
+// address (the batch workspace), the batched kernels add the base back, so
+// the compiler sees pointers derived from a global kernel argument (global
+// loads) instead of pointers read from memory (flat loads).
+template <typename R, typename F>
+__host__ __device__ inline void for_each_ptr(View<R>& v, F&& f) {
+  f(v.pos); f(v.cell); f(v.u); f(v.a); f(v.T); f(v.m); f(v.id); f(v.info); f(v.aux); f(v.ud);
+  f(v.u_out); f(v.T_out); f(v.rho); f(v.p); f(v.pw); f(v.uw); f(v.dTdt); f(v.ab); f(v.vp); f(v.rm); f(v.pa);
+  f(v.cstart); f(v.s_rb); f(v.s_rk); f(v.s_f); f(v.s_aw); f(v.s_x); f(v.s_m); f(v.s_sorted); f(v.s_body);
+  f(v.s_id); f(v.w_x0); f(v.w_aw); f(v.w_sorted); f(v.mat); f(v.bodies); f(v.err); f(v.pairs);
+  f(v.nb.table); f(v.nb.nwaves); f(v.nb.ent); f(v.nb.cnt); f(v.nb.split); f(v.nb.ext); f(v.nb.ext_n);
+  f(v.nb.jlo); f(v.dyn); f(v.dstep);
+  f(v.ps.flag); f(v.ps.target); f(v.ps.label); f(v.ps.body_of_id); f(v.ps.list); f(v.ps.roots); f(v.ps.ctr);
+  f(v.ps.dirty); f(v.ps.rold); f(v.ps.alive); f(v.ps.alive_sc); f(v.ps.bsum); f(v.ps.jkey[0]); f(v.ps.jkey[1]);
+  f(v.ps.jidx[0]); f(v.ps.jidx[1]); f(v.ps.snew); f(v.ps.sbody); f(v.ps.sid); f(v.ps.srb); f(v.ps.srk);
+  f(v.ps.srf);
+}
+
 struct SortBufs {
   uint32_t* key;
   uint32_t* rank;
@@ -227,8 +246,9 @@ struct Launch {
   static void extrapolate(const View<R>& v, const Params& P, const KC<R>& k, hipStream_t st);
   static void forces(const View<R>& v, const Params& P, const KC<R>& k, int kick, int heat, hipStream_t st);
   // stage 0 density, 1 extrapolation, 2 forces, over all slots of the table
-  static void batch_sweep(int stage, const Slot<R>* tab, int ns, int dim, int mode, uint32_t blocks, int kick,
-                          int heat, hipStream_t st);
+  // tab: slot table whose view pointers are offsets from gbase
+  static void batch_sweep(int stage, const Slot<R>* tab, const char* gbase, int ns, int dim, int mode,
+                          uint32_t blocks, int kick, int heat, hipStream_t st);
   static void rigid_velocity(const View<R>& v, const Params& P, hipStream_t st);
   static void global_sums(const View<R>& v, const Params& P, double* partials, int nblocks, double* out, hipStream_t st);
   static void nb_count(const View<R>& v, const Params& P, const KC<R>& k, uint32_t* cnt, hipStream_t st);

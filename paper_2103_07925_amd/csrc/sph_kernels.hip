@@ -1161,6 +1161,17 @@ __global__ void __launch_bounds__(64) k_forces_list(View<R> v, Params P, KC<R> k
 // exactly the code of the single-scene kernels.
 // ---------------------------------------------------------------------------
 
+// a slot's view with its offsets turned back into pointers from gbase
+template <typename R>
+__device__ __forceinline__ View<R> slot_view(const Slot<R>& S, const char* gbase) {
+  View<R> v = S.v;
+  for_each_ptr(v, [&](auto*& p) {
+    using T = std::remove_reference_t<decltype(*p)>;
+    p = reinterpret_cast<T*>(const_cast<char*>(gbase) + reinterpret_cast<intptr_t>(p));
+  });
+  return v;
+}
+
 template <typename R>
 __device__ __forceinline__ int find_slot(const Slot<R>* tab, int ns, uint32_t b) {
   int lo = 0, hi = ns;
@@ -1173,27 +1184,28 @@ __device__ __forceinline__ int find_slot(const Slot<R>* tab, int ns, uint32_t b)
 }
 
 template <typename R, int DIM>
-__global__ void __launch_bounds__(64) k_build_density_batch(const Slot<R>* tab, int ns) {
+__global__ void __launch_bounds__(64) k_build_density_batch(const Slot<R>* tab, const char* gbase, int ns) {
   const Slot<R>& S = tab[find_slot<R>(tab, ns, blockIdx.x)];
-  const View<R> v = S.v;
+  const View<R> v = slot_view<R>(S, gbase);
   const Params P = S.P;
   const KC<R> k = S.k;
   build_density_wave<R, DIM>(v, P, k, xcd_wave((int)(blockIdx.x - S.b0), (int)S.nb));
 }
 
 template <typename R, int DIM>
-__global__ void __launch_bounds__(64) k_extrapolate_batch(const Slot<R>* tab, int ns) {
+__global__ void __launch_bounds__(64) k_extrapolate_batch(const Slot<R>* tab, const char* gbase, int ns) {
   const Slot<R>& S = tab[find_slot<R>(tab, ns, blockIdx.x)];
-  const View<R> v = S.v;
+  const View<R> v = slot_view<R>(S, gbase);
   const Params P = S.P;
   const KC<R> k = S.k;
   extrapolate_wave<R, DIM>(v, P, k, (int)(blockIdx.x - S.b0), (int)S.nb);
 }
 
 template <typename R, int DIM, int THERMAL, int TVF>
-__global__ void __launch_bounds__(64) k_forces_batch(const Slot<R>* tab, int ns, int kick, int heat) {
+__global__ void __launch_bounds__(64) k_forces_batch(const Slot<R>* tab, const char* gbase, int ns, int kick,
+                                                     int heat) {
   const Slot<R>& S = tab[find_slot<R>(tab, ns, blockIdx.x)];
-  const View<R> v = S.v;
+  const View<R> v = slot_view<R>(S, gbase);
   const Params P = S.P;
   const KC<R> k = S.k;
   forces_wave<R, DIM, THERMAL, TVF>(v, P, k, xcd_wave((int)(blockIdx.x - S.b0), (int)S.nb), kick, heat);
@@ -2142,26 +2154,26 @@ void Launch<R>::forces(const View<R>& v, const Params& P, const KC<R>& k, int ki
   }
 }
 template <typename R>
-void Launch<R>::batch_sweep(int stage, const Slot<R>* tab, int ns, int dim, int mode, uint32_t blocks, int kick,
-                            int heat, hipStream_t st) {
+void Launch<R>::batch_sweep(int stage, const Slot<R>* tab, const char* gbase, int ns, int dim, int mode,
+                            uint32_t blocks, int kick, int heat, hipStream_t st) {
   if (ns <= 0 || blocks == 0) return;
   if (stage == 0) {
-    if (dim == 2) k_build_density_batch<R, 2><<<blocks, 64, 0, st>>>(tab, ns);
-    else k_build_density_batch<R, 3><<<blocks, 64, 0, st>>>(tab, ns);
+    if (dim == 2) k_build_density_batch<R, 2><<<blocks, 64, 0, st>>>(tab, gbase, ns);
+    else k_build_density_batch<R, 3><<<blocks, 64, 0, st>>>(tab, gbase, ns);
   } else if (stage == 1) {
-    if (dim == 2) k_extrapolate_batch<R, 2><<<blocks, 64, 0, st>>>(tab, ns);
-    else k_extrapolate_batch<R, 3><<<blocks, 64, 0, st>>>(tab, ns);
+    if (dim == 2) k_extrapolate_batch<R, 2><<<blocks, 64, 0, st>>>(tab, gbase, ns);
+    else k_extrapolate_batch<R, 3><<<blocks, 64, 0, st>>>(tab, gbase, ns);
   } else {
     // mode: bit 0 thermal, bit 1 transport-velocity formulation
     switch ((mode & 3) | (dim == 3 ? 4 : 0)) {
-      case 0: k_forces_batch<R, 2, 0, 0><<<blocks, 64, 0, st>>>(tab, ns, kick, heat); break;
-      case 1: k_forces_batch<R, 2, 1, 0><<<blocks, 64, 0, st>>>(tab, ns, kick, heat); break;
-      case 2: k_forces_batch<R, 2, 0, 1><<<blocks, 64, 0, st>>>(tab, ns, kick, heat); break;
-      case 3: k_forces_batch<R, 2, 1, 1><<<blocks, 64, 0, st>>>(tab, ns, kick, heat); break;
-      case 4: k_forces_batch<R, 3, 0, 0><<<blocks, 64, 0, st>>>(tab, ns, kick, heat); break;
-      case 5: k_forces_batch<R, 3, 1, 0><<<blocks, 64, 0, st>>>(tab, ns, kick, heat); break;
-      case 6: k_forces_batch<R, 3, 0, 1><<<blocks, 64, 0, st>>>(tab, ns, kick, heat); break;
-      default: k_forces_batch<R, 3, 1, 1><<<blocks, 64, 0, st>>>(tab, ns, kick, heat); break;
+      case 0: k_forces_batch<R, 2, 0, 0><<<blocks, 64, 0, st>>>(tab, gbase, ns, kick, heat); break;
+      case 1: k_forces_batch<R, 2, 1, 0><<<blocks, 64, 0, st>>>(tab, gbase, ns, kick, heat); break;
+      case 2: k_forces_batch<R, 2, 0, 1><<<blocks, 64, 0, st>>>(tab, gbase, ns, kick, heat); break;
+      case 3: k_forces_batch<R, 2, 1, 1><<<blocks, 64, 0, st>>>(tab, gbase, ns, kick, heat); break;
+      case 4: k_forces_batch<R, 3, 0, 0><<<blocks, 64, 0, st>>>(tab, gbase, ns, kick, heat); break;
+      case 5: k_forces_batch<R, 3, 1, 0><<<blocks, 64, 0, st>>>(tab, gbase, ns, kick, heat); break;
+      case 6: k_forces_batch<R, 3, 0, 1><<<blocks, 64, 0, st>>>(tab, gbase, ns, kick, heat); break;
+      default: k_forces_batch<R, 3, 1, 1><<<blocks, 64, 0, st>>>(tab, gbase, ns, kick, heat); break;
     }
   }
 }
