@@ -65,7 +65,7 @@ class Desc(C.Structure):
                 ("heat_src", C.c_int32), ("pad1", C.c_int32),
                 ("src_Q", C.c_double), ("src_sigma", C.c_double), ("src_s0", C.c_double * 2),
                 ("src_v", C.c_double * 2), ("src_ztop", C.c_double), ("src_depth", C.c_double),
-                ("p_b", C.c_double)]
+                ("p_b", C.c_double), ("periodic", C.c_int32 * 3), ("pad2", C.c_int32)]
 
 
 _lib = None
@@ -177,6 +177,8 @@ class _DescHolder:
             d.src_v[a] = sc.src_v[a]
         d.src_ztop, d.src_depth = sc.src_ztop, sc.src_depth
         d.p_b = getattr(sc, "p_b", 0.0)
+        for a in range(3):
+            d.periodic[a] = int(getattr(sc, "periodic", (0, 0, 0))[a])
         self.desc = d
 
 

@@ -64,6 +64,8 @@ struct orc_scene {
   double sQ, ssig, ss0[2], sv[2], sztop, sdepth;
   int tvf;
   double pb;
+  int per[3];        /* periodic axes */
+  double period[3];
   int64_t pairs;
   /* scratch */
   nb_t *nbuf;
@@ -430,6 +432,8 @@ static int build_cells(orc_scene *s) {
     int c3[3] = {0, 0, 0};
     for (int a = 0; a < s->dim; ++a) {
       double v = floor((s->x[3 * i + a] - s->lo[a]) / s->L);
+      /* a wrapped coordinate a rounding below lo + period stays in the last cell */
+      if (s->per[a] && v == (double)s->nc[a]) v = (double)(s->nc[a] - 1);
       if (!(v >= 0.0) || v >= (double)s->nc[a]) return ORC_E_STATE;
       c3[a] = (int)v;
     }
@@ -459,7 +463,10 @@ static int build_cells(orc_scene *s) {
 }
 
 /* Neighbours j of particle i with |x_i - x_j|^2 < r_c^2, in canonical
- * gather order; i itself is included only when with_self is set. */
+ * gather order; i itself is included only when with_self is set.  Along a
+ * periodic axis the stencil wraps and a neighbour across the boundary is
+ * taken at its image x_j +- period (the nearest one: the grid has at least
+ * three cells along the axis). */
 static int64_t gather(const orc_scene *s, int64_t i, int with_self) {
   int64_t lin = s->cell[i];
   int ci[3];
@@ -473,15 +480,20 @@ static int64_t gather(const orc_scene *s, int64_t i, int with_self) {
     for (int dy = -1; dy <= 1; ++dy)
       for (int dxx = -1; dxx <= 1; ++dxx) {
         int cx = ci[0] + dxx, cy = ci[1] + dy, cz = ci[2] + dz;
+        double sh1 = 0.0, sh2 = 0.0;
+        if (s->per[1] && cy < 0) { cy += s->nc[1]; sh1 = -s->period[1]; }
+        if (s->per[1] && cy >= s->nc[1]) { cy -= s->nc[1]; sh1 = s->period[1]; }
+        if (s->per[2] && cz < 0) { cz += s->nc[2]; sh2 = -s->period[2]; }
+        if (s->per[2] && cz >= s->nc[2]) { cz -= s->nc[2]; sh2 = s->period[2]; }
         if (cx < 0 || cy < 0 || cz < 0 || cx >= s->nc[0] || cy >= s->nc[1] || cz >= s->nc[2]) continue;
         int64_t c = (int64_t)cx + (int64_t)s->nc[0] * ((int64_t)cy + (int64_t)s->nc[1] * cz);
         for (int64_t k = s->cstart[c]; k < s->cstart[c + 1]; ++k) {
           int32_t j = s->cids[k];
           if (j == i && !with_self) continue;
           const double *xj = &s->x[3 * j];
-          double d0 = xi[0] - xj[0], d1 = xi[1] - xj[1], d2 = 0.0;
+          double d0 = xi[0] - xj[0], d1 = xi[1] - (xj[1] + sh1), d2 = 0.0;
           double r2 = d0 * d0 + d1 * d1;
-          if (s->dim == 3) { d2 = xi[2] - xj[2]; r2 = r2 + d2 * d2; }
+          if (s->dim == 3) { d2 = xi[2] - (xj[2] + sh2); r2 = r2 + d2 * d2; }
           if (r2 < s->rc2) {
             nb_t *e = &s->nbuf[cnt++];
             e->j = j; e->d[0] = d0; e->d[1] = d1; e->d[2] = d2; e->r2 = r2;
@@ -807,6 +819,15 @@ static int body_recompute(orc_scene *s, int k) {
 /* Rigid particle positions and velocities from their body (the drift step
  * of Sec. "Time integration"): r_rk = R(q_k) r_rk^b, x_r = r_k + r_rk,
  * u_r = u_k + omega_k x r_rk. */
+/* a position along the periodic axes back into [lo, lo + period) */
+static void wrap_pos(const orc_scene *s, double *x) {
+  for (int a = 1; a < s->dim; ++a) {
+    if (!s->per[a]) continue;
+    if (x[a] >= s->lo[a] + s->period[a]) x[a] = x[a] - s->period[a];
+    else if (x[a] < s->lo[a]) x[a] = x[a] + s->period[a];
+  }
+}
+
 static void rigid_pose(orc_scene *s) {
   for (int k = 0; k < s->nb; ++k) {
     if (!s->bactive[k]) continue;
@@ -822,6 +843,7 @@ static void rigid_pose(orc_scene *s) {
         s->rk[3 * i + a] = rk[a];
         s->x[3 * i + a] = (a < s->dim) ? s->br[3 * k + a] + rk[a] : 0.0;
       }
+      wrap_pos(s, &s->x[3 * i]);
       for (int a = 0; a < 3; ++a) s->u[3 * i + a] = (a < s->dim) ? s->bu[3 * k + a] + wr[a] : 0.0;
     }
   }
@@ -1169,6 +1191,19 @@ int orc_create(const orc_desc *d, orc_scene **out) {
   s->sztop = d->src_ztop; s->sdepth = d->src_depth;
   s->tvf = d->p_b > 0.0;
   s->pb = s->tvf ? d->p_b : 0.0;
+  /* periodic axes: y and z only, a whole number (>= 3) of cells per period,
+   * no phase switching (the body quantities of a switch are not taken
+   * across the boundary) */
+  for (int a = 0; a < 3; ++a) {
+    s->per[a] = (a < s->dim) ? (d->periodic[a] != 0) : 0;
+    s->period[a] = s->per[a] ? d->hi[a] - d->lo[a] : 0.0;
+    if (!s->per[a]) continue;
+    double whole = (double)s->nc[a] * s->L;
+    if (a == 0 || s->nc[a] < 3 || fabs(whole - s->period[a]) > 1e-9 * s->period[a] || d->phase_switch) {
+      orc_destroy(s);
+      return ORC_E_INVALID;
+    }
+  }
   /* time step and contact constants */
   double mmin;
   double dt0 = timestep_without_contact(d, &mmin);
@@ -1200,6 +1235,9 @@ int orc_create(const orc_desc *d, orc_scene **out) {
   rigid_velocities(s);
   for (int64_t i = 0; i < n; ++i)
     if (s->moving[i]) for (int a = 0; a < 3; ++a) s->u[3 * i + a] = 0.0;
+  /* body quantities came from the positions as given (a body may extend
+   * across a periodic boundary); every position now into the periodic box */
+  for (int64_t i = 0; i < n; ++i) wrap_pos(s, &s->x[3 * i]);
   /* one evaluation without time update gives a^0 and the body accelerations */
   st = evaluate(s, 0);
   if (st != ORC_OK) { orc_destroy(s); return st; }
@@ -1220,6 +1258,7 @@ static void wall_motion(orc_scene *s, double t) {
       s->u[3 * i + a] = vA * s->wall_dir[a];
       s->aw[3 * i + a] = aA * s->wall_dir[a];
     }
+    wrap_pos(s, &s->x[3 * i]);
   }
 }
 
@@ -1242,7 +1281,7 @@ static int one_step(orc_scene *s) {
   /* drift; with the transport-velocity formulation fluid particles move
    * with u~^{n+1/2} = u^{n+1/2} + (dt/2) a_b^n */
   for (int64_t i = 0; i < s->n; ++i)
-    if (s->kind[i] == ORC_FLUID)
+    if (s->kind[i] == ORC_FLUID) {
       for (int a = 0; a < s->dim; ++a) {
         double v = s->u[3 * i + a];
         if (s->tvf) {
@@ -1251,6 +1290,8 @@ static int one_step(orc_scene *s) {
         }
         s->x[3 * i + a] = s->x[3 * i + a] + s->dt * v;
       }
+      wrap_pos(s, &s->x[3 * i]);
+    }
   for (int k = 0; k < s->nb; ++k) {
     if (!s->bactive[k] || s->bfixed[k]) continue;
     for (int a = 0; a < 3; ++a) s->br[3 * k + a] = s->br[3 * k + a] + s->dt * s->bu[3 * k + a];

@@ -66,6 +66,8 @@ typedef struct {
   int32_t pad1;
   double src_Q, src_sigma, src_s0[2], src_v[2], src_ztop, src_depth;
   double p_b;                /* background pressure of the transport-velocity formulation; 0: off */
+  int32_t periodic[3];       /* periodic axes (y and z only); the extent must be a whole number of cells */
+  int32_t pad2;
 } orc_desc;
 
 typedef struct orc_scene orc_scene;

@@ -84,6 +84,7 @@ class Scene:
     src_ztop: float = 0.0
     src_depth: float = 0.0
     p_b: float = 0.0         # background pressure of the transport-velocity formulation; 0: off
+    periodic: tuple = (0, 0, 0)  # periodic axes (y, z only); extent a whole number of cells
     meta: dict = field(default_factory=dict)
 
     @property
@@ -502,6 +503,62 @@ def config_gastric(seed: int = 0, dx: float = 0.1, size=(40.0, 16.0), n_bolus: i
                    wall_dir=(1.0, 0.0, 0.0))
     sc.x = jitter(sc.x, sc.kind == FLUID, dx, rng, dim)
     sc.p_b = pb_factor * p0
+    sc.meta.update(seed=seed, c=c)
+    return sc
+
+
+def periodic_channel(dim: int = 2, n_sites=(20, 12, 9), dx: float = 0.05, g: float = 1.0, nu: float = 0.5,
+                     c: float = 2.5, rho0: float = 1.0, seed: int = 0, jitter_amp: float = 0.01,
+                     body_radius: float = 0.0, body_centre=None, body_density: float = 2.0) -> Scene:
+    """Channel between two 3-layer walls normal to x (at x = 0 and x = n_x dx),
+    periodic along y (and z in 3D) with periods n_y dx (n_z dx), which must
+    be multiples of 3 sites (whole cells of edge 3 dx); body force g along y
+    (a Poiseuille flow).  Optionally one rigid disc / sphere of body_radius
+    around body_centre (which may straddle a periodic boundary)."""
+    rng = np.random.default_rng(seed)
+    nx, ny = int(n_sites[0]), int(n_sites[1])
+    nz = int(n_sites[2]) if dim == 3 else 1
+    if ny % 3 or (dim == 3 and nz % 3):
+        raise ValueError("periodic extents must be whole cells (multiples of 3 sites)")
+    layers = 3
+    lo_idx = [0, 0, 0][:dim]
+    hi_idx = [nx, ny, nz][:dim]
+    inner = lattice_sites(dim, lo_idx, hi_idx, dx)
+    wl = lattice_sites(dim, [-layers] + lo_idx[1:], [0] + hi_idx[1:], dx)
+    wr = lattice_sites(dim, [nx] + lo_idx[1:], [nx + layers] + hi_idx[1:], dx)
+    walls = np.concatenate([wl, wr])
+    gvec = [0.0, 0.0, 0.0]
+    gvec[1] = g
+    mats = [Material(rho0=rho0, p0=rho0 * c * c, nu=nu, b=tuple(gvec)), Material(rho0=rho0),
+            Material(rho0=body_density * rho0, b=tuple(gvec))]
+    kind_of = np.full(inner.shape[0], FLUID, np.int32)
+    bodies = []
+    groups = []
+    if body_radius > 0.0:
+        cen = np.zeros(3)
+        cen[:dim] = np.asarray(body_centre, dtype=np.float64)[:dim]
+        per = np.array([0.0, ny * dx, nz * dx])
+        # the body's sites, taken by minimum image, listed contiguously (they
+        # may reach beyond the periodic box; set-up wraps them)
+        d = inner - cen
+        for a in (1, 2)[:dim - 1]:
+            d[:, a] -= per[a] * np.round(d[:, a] / per[a])
+        sel = np.sum(d[:, :dim] ** 2, axis=1) <= body_radius ** 2
+        kind_of[sel] = RIGID
+        groups.append((cen + d[sel], RIGID, 2, 0, 0, 0.0))
+        bodies.append(BodyInit())
+    groups.insert(0, (inner[kind_of == FLUID], FLUID, 0, -1, 0, 0.0))
+    groups.append((walls, WALL, 1, -1, 0, 0.0))
+    lo = np.zeros(3)
+    hi = np.zeros(3)
+    lo[0], hi[0] = -layers * dx, (nx + layers) * dx
+    lo[1], hi[1] = 0.0, ny * dx
+    if dim == 3:
+        lo[2], hi[2] = 0.0, nz * dx
+    sc = _assemble(f"channel{dim}d", dim, dx, lo, hi, groups, mats, bodies, max_bodies=len(bodies))
+    sc.periodic = (0, 1, 1 if dim == 3 else 0)
+    if jitter_amp > 0:
+        sc.x = jitter(sc.x, sc.kind == FLUID, dx, rng, dim, jitter_amp)
     sc.meta.update(seed=seed, c=c)
     return sc
 
