@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 2
+#define SPH_ABI_VERSION 3
 
 enum {
   SPH_OK = 0,
@@ -123,6 +123,15 @@ typedef struct {
    * A = rho u (u~ - u) to the momentum equation.  0: off (the printed
    * momentum equation only); the paper's examples use p_b = p0. */
   double p_b;
+  /* Periodic axes (y and z only; x is the axis of the wave rows): the
+   * extent hi - lo of a periodic axis is its period and must be a whole
+   * number (>= 3) of cells; neighbours across the boundary are taken at
+   * their image, positions are kept inside the box, a rigid body may
+   * straddle the boundary (give its particles contiguous positions: its
+   * centre of mass and frame come from them) and its centre of mass is not
+   * wrapped.  Not combined with phase switching. */
+  int32_t periodic[3];
+  int32_t pad2;
 } sph_scene_desc;
 
 typedef struct sph_scene sph_scene;

@@ -413,6 +413,20 @@ int make_params(const sph_scene_desc* d, Params& P, double* m_min) {
   if (!(d->p_b >= 0.0) || !std::isfinite(d->p_b)) return fail(SPH_E_INVALID, "background pressure p_b must be >= 0");
   P.tvf = d->p_b > 0.0 ? 1 : 0;
   P.pb = P.tvf ? d->p_b : 0.0;
+  // periodic axes: y and z only (waves run along x rows), a whole number of
+  // at least 3 cells per period, no phase switching
+  for (int a = 0; a < 3; ++a) {
+    P.per[a] = (a < d->dim && d->periodic[a]) ? 1 : 0;
+    P.period[a] = P.per[a] ? d->hi[a] - d->lo[a] : 0.0;
+  }
+  if (P.per[0]) return fail(SPH_E_UNSUPPORTED, "the x axis cannot be periodic (make a periodic direction y or z)");
+  for (int a = 1; a < 3; ++a) {
+    if (!P.per[a]) continue;
+    if (P.nc[a] < 3) return fail(SPH_E_INVALID, "a periodic axis needs at least 3 cells");
+    if (std::fabs((double)P.nc[a] * P.L - P.period[a]) > 1e-9 * P.period[a])
+      return fail(SPH_E_INVALID, "a periodic extent must be a whole number of cells");
+    if (d->phase_switch) return fail(SPH_E_UNSUPPORTED, "phase switching with periodic axes");
+  }
   P.n_mat = d->n_mat;
   P.nb = d->n_body;
   P.maxb = std::max(d->max_bodies, d->n_body);
@@ -447,6 +461,8 @@ KC<R> make_kc(const Params& P) {
   k.dt = (R)P.dt;
   k.hdt = (R)P.hdt;
   k.pb = (R)P.pb;
+  k.per_y = (R)P.period[1];
+  k.per_z = (R)P.period[2];
   for (int a = 0; a < 3; ++a) k.lo[a] = (R)P.lo[a];
   return k;
 }
@@ -772,10 +788,19 @@ int create_impl(const sph_scene_desc* d, sph_scene* s) {
     const int moving = (kind == SPH_WALL && d->moving && d->moving[i]) ? 1 : 0;
     const int body = kind == SPH_RIGID ? d->body[i] : -1;
     double x[3] = {d->x[3 * i], d->x[3 * i + 1], d->dim == 3 ? d->x[3 * i + 2] : 0.0};
+    // the position binned: along periodic axes wrapped into the box (body
+    // quantities and moving-wall references keep the position as given)
+    double xw[3] = {x[0], x[1], x[2]};
+    for (int ax = 1; ax < P.dim; ++ax) {
+      if (!P.per[ax]) continue;
+      if (xw[ax] >= P.lo[ax] + P.period[ax]) xw[ax] = xw[ax] - P.period[ax];
+      else if (xw[ax] < P.lo[ax]) xw[ax] = xw[ax] + P.period[ax];
+    }
     // cell of the initial position
     int c3[3] = {0, 0, 0};
     for (int ax = 0; ax < P.dim; ++ax) {
-      double vv = std::floor((x[ax] - P.lo[ax]) / P.L);
+      double vv = std::floor((xw[ax] - P.lo[ax]) / P.L);
+      if (P.per[ax] && vv == (double)P.nc[ax]) vv = (double)(P.nc[ax] - 1);
       if (!(vv >= 0.0) || vv >= (double)P.nc[ax])
         return fail(SPH_E_INVALID, "particle " + std::to_string(i) + " outside the cell grid");
       c3[ax] = (int)vv;
@@ -784,11 +809,11 @@ int create_impl(const sph_scene_desc* d, sph_scene* s) {
     cell[i] = lin;
     V4<R> o;
     if (sizeof(R) == 8) {
-      o.x = (R)x[0]; o.y = (R)x[1]; o.z = (R)x[2]; o.w = 0;
+      o.x = (R)xw[0]; o.y = (R)xw[1]; o.z = (R)xw[2]; o.w = 0;
     } else {
       R off[3] = {0, 0, 0};
       for (int ax = 0; ax < P.dim; ++ax) {
-        double rel = (x[ax] - P.lo[ax]) - (double)c3[ax] * P.L;
+        double rel = (xw[ax] - P.lo[ax]) - (double)c3[ax] * P.L;
         float f = (float)rel;
         off[ax] = f < 0.f ? 0.f : (f > (float)P.L ? (float)P.L : f);
       }

@@ -86,6 +86,8 @@ struct Params {
   int64_t ext_cap;      // wall and rigid particles at most (extrapolation targets)
   int tvf;              // transport-velocity formulation on
   double pb;            // its background pressure
+  int per[3];           // periodic axes (y and z only)
+  double period[3];     // their periods (a whole number of cells)
 };
 
 // one wavefront of the sweeps: up to 64 consecutive sorted particles of one
@@ -113,6 +115,7 @@ struct Lists {
 template <typename R>
 struct KC {
   R h, inv_h, wnorm, dnorm, rc2, L, dx, dx2, vol0, kc, dc, dt, hdt, pb;
+  R per_y, per_z;   // periods of the periodic axes (0 otherwise)
   R lo[3];
 };
 

@@ -132,11 +132,22 @@ __device__ __forceinline__ DD dd_merge(DD a, DD b) {
 __device__ __forceinline__ void set_err(uint32_t* err, uint32_t bit) { atomicOr(err, bit); }
 
 // linear cell index of an FP64 position, or -1 outside the grid
+// a position along the periodic axes back into [lo, lo + period)
+__device__ __forceinline__ void wrap_pos(const Params& P, double* x) {
+  for (int a = 1; a < P.dim; ++a) {
+    if (!P.per[a]) continue;
+    if (x[a] >= P.lo[a] + P.period[a]) x[a] = x[a] - P.period[a];
+    else if (x[a] < P.lo[a]) x[a] = x[a] + P.period[a];
+  }
+}
+
 __device__ __forceinline__ long long cell_of(const Params& P, const double* x, int* c3) {
   long long lin = 0;
   c3[0] = c3[1] = c3[2] = 0;
   for (int a = 0; a < P.dim; ++a) {
     double v = floor((x[a] - P.lo[a]) / P.L);
+    // a wrapped coordinate a rounding below lo + period stays in the last cell
+    if (P.per[a] && v == (double)P.nc[a]) v = (double)(P.nc[a] - 1);
     if (!(v >= 0.0) || v >= (double)P.nc[a]) return -1;
     c3[a] = (int)v;
   }
@@ -146,8 +157,10 @@ __device__ __forceinline__ long long cell_of(const Params& P, const double* x, i
 
 // store an FP64 position into the sweep representation
 template <typename R>
-__device__ __forceinline__ void put_pos(const Params& P, const double* x, V4<R>* pos, uint32_t* cell,
+__device__ __forceinline__ void put_pos(const Params& P, const double* xin, V4<R>* pos, uint32_t* cell,
                                         uint32_t* key, int64_t i, uint32_t* err) {
+  double x[3] = {xin[0], xin[1], xin[2]};
+  wrap_pos(P, x);
   int c3[3];
   long long lin = cell_of(P, x, c3);
   if (lin < 0) {
@@ -681,6 +694,21 @@ __device__ __forceinline__ WaveGeo wave_geo(const View<R>& v, const Params& P, c
   return g;
 }
 
+// periodic image of every stencil row of a wave in cell row (cy, cz): 4 bits
+// per row (y, z: 0 image below, 1 none, 2 image above); used by the FP64 walks
+template <int DIM>
+__device__ __forceinline__ uint64_t wrap_codes(const Params& P, int cy, int cz) {
+  uint64_t wc = 0;
+  for (int rr = 0; rr < (DIM == 3 ? 9 : 3); ++rr) {
+    const int dy = rr % 3 - 1, dz = DIM == 3 ? rr / 3 - 1 : 0;
+    const int yy = cy + dy, zz = cz + dz;
+    const uint64_t ky = (P.per[1] && yy < 0) ? 0u : ((P.per[1] && yy >= P.nc[1]) ? 2u : 1u);
+    const uint64_t kz = (DIM == 3 && P.per[2] && zz < 0) ? 0u : ((DIM == 3 && P.per[2] && zz >= P.nc[2]) ? 2u : 1u);
+    wc |= (ky | (kz << 2)) << (4 * rr);
+  }
+  return wc;
+}
+
 // position in the wave's frame: FP64 absolute; FP32 relative to the origin
 // of cell (cx_first, cy, cz), from the cell-relative offset
 template <typename R>
@@ -762,9 +790,9 @@ __device__ __forceinline__ void stage_rows(R* ro, const KC<R>& k) {
 
 template <typename R, int DIM, bool PACKED, typename F>
 __device__ __forceinline__ void for_list(const View<R>& v, const KC<R>& k, const MatL<R>* sm, const R* ro,
-                                         int cx_first, const uint32_t* jl, const uint16_t* gl, int n_all, int split,
-                                         uint32_t i, const V4<R>& T, bool with_self, F&& visit, int q0 = 0,
-                                         int dq = 1) {
+                                         int cx_first, uint64_t wc, const uint32_t* jl, const uint16_t* gl,
+                                         int n_all, int split, uint32_t i, const V4<R>& T, bool with_self,
+                                         F&& visit, int q0 = 0, int dq = 1) {
   constexpr int CAP = Nb<DIM>::cap;
   constexpr bool PK = PACKED && !IsExact<R>::v;
   const int n_lane = n_all > q0 ? (n_all - q0 + dq - 1) / dq : 0;   // this lane's entries
@@ -830,7 +858,11 @@ __device__ __forceinline__ void for_list(const View<R>& v, const KC<R>& k, const
         }
         V4<R> sj;
         if constexpr (IsExact<R>::v) {
+          // periodic image of the row (a zero shift leaves the position as is)
+          const uint32_t cw = (uint32_t)(wc >> (4u * rr)) & 15u;
           sj = pj;
+          sj.y = pj.y + (R)((int)(cw & 3u) - 1) * k.per_y;
+          sj.z = pj.z + (R)((int)(cw >> 2) - 1) * k.per_z;
         } else {
           // the wave's frame (cf. to_frame): dy L and dz L are exact, so the
           // sums round like the fused forms
@@ -923,7 +955,14 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
   R sum = R(0);
   for (int rr = 0; rr < NR; ++rr) {
     const int dz = DIM == 3 ? rr / 3 - 1 : 0, dy = rr % 3 - 1;
-    const int yy = g.cy + dy, zz = g.cz + dz;
+    int yy = g.cy + dy, zz = g.cz + dz;
+    // periodic axes: the stencil row wraps; in FP64 the row's particles are
+    // taken at their image (FP32 frames are cell-relative already)
+    R shy = R(0), shz = R(0);
+    if (P.per[1] && yy < 0) { yy += ny; shy = -(R)P.period[1]; }
+    else if (P.per[1] && yy >= ny) { yy -= ny; shy = (R)P.period[1]; }
+    if (DIM == 3 && P.per[2] && zz < 0) { zz += nz; shz = -(R)P.period[2]; }
+    else if (DIM == 3 && P.per[2] && zz >= nz) { zz -= nz; shz = (R)P.period[2]; }
     uint32_t jlo = 0u, jhi = 0u, llo = 0u, lhi = 0u;
     if (yy >= 0 && yy < ny && zz >= 0 && zz < nz) {
       const uint32_t rb2 = (uint32_t)((zz * ny + yy) * nx);
@@ -940,6 +979,10 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
         V4<R> sq;
         if (q < ns) {
           sq = to_frame<R>(v.pos[seg + q], k, g.cx_first, dy, dz);
+          if constexpr (IsExact<R>::v) {
+            sq.y = sq.y + shy;
+            sq.z = sq.z + shz;
+          }
           sq.w = info_to_r(v.info[seg + q], R(0));
         } else {
           sq.x = sq.y = sq.z = -far;    // padding: never a neighbour
@@ -1101,7 +1144,8 @@ __device__ __forceinline__ void extrapolate_wave(const View<R>& v, const Params&
     const int n_f = need ? (int)v.nb.split[(size_t)w * 64 + l] : 0;
     unsigned long long cr = 0, cw = 0;
     const uint32_t c = extrap_one<R, DIM, kExtSub>(v, k, smat, i, need, sub == 0, [&](bool ws, auto&& f) {
-      for_list<R, DIM, true>(v, k, smat, ro, g.cx_first, jls + lane * NR, v.nb.ent + (size_t)w * CAP * 64 + l, n_f,
+      for_list<R, DIM, true>(v, k, smat, ro, g.cx_first, wrap_codes<DIM>(P, g.cy, g.cz), jls + lane * NR,
+                             v.nb.ent + (size_t)w * CAP * 64 + l, n_f,
                              n_f, i, T, ws, f, sub, kExtSub);
     });
     if (need && sub == 0 && kind == KR) cr = c;
@@ -1144,7 +1188,8 @@ __device__ __forceinline__ void forces_wave(const View<R>& v, const Params& P, c
   const int split = v.nb.split[(size_t)w * 64 + lane];
   const double t = (double)(*v.dstep) * P.dt;
   forces_one<R, DIM, THERMAL, TVF>(v, P, k, smat, i, need, kick, heat, t, [&](bool ws, auto&& f) {
-    for_list<R, DIM, THERMAL == 0>(v, k, smat, ro, g.cx_first, jl, v.nb.ent + (size_t)w * Nb<DIM>::cap * 64 + lane,
+    for_list<R, DIM, THERMAL == 0>(v, k, smat, ro, g.cx_first, wrap_codes<DIM>(P, g.cy, g.cz), jl,
+                                   v.nb.ent + (size_t)w * Nb<DIM>::cap * 64 + lane,
                                    n_lane, split, i, T, ws, f);
   });
 }
@@ -1302,6 +1347,9 @@ __global__ void __launch_bounds__(256) k_kick_drift(View<R> v, Params P, KC<R> k
       x.y = x.y + k.dt * w.y;
       if (P.dim == 3) x.z = x.z + k.dt * w.z;
       double xx[3] = {x.x, x.y, x.z};
+      wrap_pos(P, xx);
+      x.y = xx[1];
+      if (P.dim == 3) x.z = xx[2];
       int c3[3];
       long long lin = cell_of(P, xx, c3);
       if (lin < 0) { set_err(v.err, ERR_ESCAPE); lin = c; }
@@ -1325,7 +1373,8 @@ __global__ void __launch_bounds__(256) k_kick_drift(View<R> v, Params P, KC<R> k
           } else {
             const int ish = (int)sh;
             o[a] = o[a] - sh * k.L;
-            if (ish < -c3[a] || ish > P.nc[a] - 1 - c3[a]) esc = true;
+            if (P.per[a]) c3[a] = ((c3[a] + ish) % P.nc[a] + P.nc[a]) % P.nc[a];   // through the periodic boundary
+            else if (ish < -c3[a] || ish > P.nc[a] - 1 - c3[a]) esc = true;
             else c3[a] += ish;
           }
         }

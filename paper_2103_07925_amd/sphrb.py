@@ -23,7 +23,7 @@ SPH_FP64, SPH_FP32_SWEEP = 0, 1
 SPH_FLUID, SPH_WALL, SPH_RIGID = 0, 1, 2
 SPH_ERR_ESCAPE, SPH_ERR_CELL, SPH_ERR_NONFINITE, SPH_ERR_COINCIDENT, SPH_ERR_BODYCAP = 1, 2, 4, 8, 16
 SPH_BODY_REC = 36
-ABI_VERSION = 2
+ABI_VERSION = 3
 FIELDS = ["X", "U", "A", "RHO", "P", "T", "PW", "UW", "FR", "M", "DTDT", "AB", "UD"]
 FIELD_BIT = {f: 1 << k for k, f in enumerate(FIELDS)}
 VEC_FIELDS = {"X", "U", "A", "UW", "FR", "AB", "UD"}
@@ -58,7 +58,7 @@ class sph_scene_desc(C.Structure):
                 ("heat_src", C.c_int32), ("pad1", C.c_int32),
                 ("src_Q", C.c_double), ("src_sigma", C.c_double), ("src_s0", C.c_double * 2),
                 ("src_v", C.c_double * 2), ("src_ztop", C.c_double), ("src_depth", C.c_double),
-                ("p_b", C.c_double)]
+                ("p_b", C.c_double), ("periodic", C.c_int32 * 3), ("pad2", C.c_int32)]
 
 
 class sph_stats(C.Structure):
@@ -207,6 +207,8 @@ class Desc:
             d.src_v[a] = sc.src_v[a]
         d.src_ztop, d.src_depth = sc.src_ztop, sc.src_depth
         d.p_b = getattr(sc, "p_b", 0.0)
+        for a in range(3):
+            d.periodic[a] = int(getattr(sc, "periodic", (0, 0, 0))[a])
         self.desc = d
 
 

@@ -22,7 +22,7 @@ def test_exports_every_header_symbol(L):
 
 
 def test_version_and_status(L):
-    assert B.sph_abi_version() == 2
+    assert B.sph_abi_version() == 3
     assert B.sph_status_string(B.SPH_E_INVALID) == "invalid argument"
 
 
@@ -76,6 +76,29 @@ def test_scene_limits_rejected(mutate, status, what):
     option have set-up conditions; a descriptor that breaks one is refused
     before any device call."""
     sc = S.config_c1()
+    mutate(sc)
+    with pytest.raises(B.SphError) as e:
+        B.sph_scene_arena_bytes(B.Desc(sc, B.SPH_FP32_SWEEP))
+    assert e.value.status == getattr(B, "SPH_E_" + status)
+    assert what in B.sph_last_error()
+
+
+def _periodic(sc, axes, ny=None):
+    sc.periodic = axes
+    if ny is not None:
+        sc.hi[1] = sc.lo[1] + ny * 3.0 * sc.dx
+    return sc
+
+
+@pytest.mark.parametrize("mutate,status,what", [
+    (lambda sc: _periodic(sc, (1, 0, 0)), "UNSUPPORTED", "x axis"),
+    (lambda sc: _periodic(sc, (0, 1, 0), ny=2), "INVALID", "at least 3 cells"),
+    (lambda sc: setattr(sc, "hi", sc.hi + np.array([0.0, 0.01, 0.0])) or _periodic(sc, (0, 1, 0)), "INVALID",
+     "whole number of cells"),
+])
+def test_periodic_limits_rejected(mutate, status, what):
+    sc = S.periodic_channel(dim=2, n_sites=(12, 9, 1), dx=0.1)
+    sc.periodic = (0, 0, 0)
     mutate(sc)
     with pytest.raises(B.SphError) as e:
         B.sph_scene_arena_bytes(B.Desc(sc, B.SPH_FP32_SWEEP))
