@@ -86,7 +86,7 @@ struct sph_scene {
   int32_t* aux[2];
   int ip, iu, iT;
   void* ud[2];       // transport-velocity formulation: u~ - u (permuted with pos)
-  void *rho, *p, *pw, *uw, *dTdt, *vp, *rm, *pa, *ab;
+  void *rho, *p, *pw, *uw, *dTdt, *pv, *rm, *ab;
   SortBufs sb;
   uint32_t* cstart;
   V4<double> *s_rb, *s_rk, *s_f, *s_aw, *s_x;
@@ -274,8 +274,7 @@ void carve(Carver& cv, sph_scene* s, const Params& P, int64_t nmat) {
   s->pw = cv.take<R>(n);
   s->uw = cv.take<V4<R>>(n);
   s->dTdt = cv.take<R>(n);
-  s->vp = cv.take<V4<R>>(n);
-  s->pa = cv.take<V4<R>>(n);
+  s->pv = cv.take<V4<R>>(2 * n);
   s->rm = cv.take<V4<R>>(n);
   s->sb.key = cv.take<uint32_t>(n);
   s->sb.rank = cv.take<uint32_t>(n);
@@ -488,8 +487,7 @@ View<R> make_view(sph_scene* s, int ip, int iu, int iT) {
   v.pw = (R*)s->pw;
   v.uw = (V4<R>*)s->uw;
   v.dTdt = (R*)s->dTdt;
-  v.vp = (V4<R>*)s->vp;
-  v.pa = (V4<R>*)s->pa;
+  v.pv = (V4<R>*)s->pv;
   v.rm = (V4<R>*)s->rm;
   v.cstart = s->cstart;
   v.s_rb = s->s_rb;

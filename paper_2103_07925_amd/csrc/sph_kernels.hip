@@ -360,7 +360,7 @@ __device__ __forceinline__ uint32_t extrap_one(const View<R>& v, const KC<R>& k,
   o.w = pw;
   v.pw[i] = pw;
   v.uw[i] = o;
-  v.vp[i] = o;
+  v.pv[2 * (size_t)i + 1] = o;
   if (kind == KR) v.p[i] = pw;
   return c;
 }
@@ -503,7 +503,7 @@ __device__ __forceinline__ void forces_one(const View<R>& v, const Params& P, co
   const R p_i = v.p[i];
   const R eta_i = Mi.eta;
   const R ka = Mi.kappa;
-  const V4<R> vpr = v.vp[i];
+  const V4<R> vpr = v.pv[2 * (size_t)i + 1];
   const R pw_r = vpr.w;
   const int body_i = ibody(inf);
   V4<R> udi;
@@ -807,11 +807,11 @@ __device__ __forceinline__ void for_list(const View<R>& v, const KC<R>& k, const
   auto fetch = [&](uint32_t e, NbRec<R>& r) {
     const uint32_t j = index(e);
     if constexpr (PK) {
-      r.a = v.pa[j];
-      r.vp = v.vp[j];
+      r.a = v.pv[2 * (size_t)j];
+      r.vp = v.pv[2 * (size_t)j + 1];
     } else {
       r.a = v.pos[j];
-      r.vp = v.vp[j];
+      r.vp = v.pv[2 * (size_t)j + 1];
       r.rm = v.rm[j];
     }
   };
@@ -1077,7 +1077,7 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
       v.p[i] = p;
       V4<R> vp = v.u[i];
       vp.w = p;
-      v.vp[i] = vp;
+      v.pv[2 * (size_t)i + 1] = vp;
       pairs = (unsigned long long)(cnt - 1);
     } else {
       rho = kind == KR ? M.rho0 : R(0);
@@ -1092,7 +1092,7 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
       pa.y = po.y;
       pa.z = po.z;
       pa.w = __uint_as_float(pk);
-      v.pa[i] = pa;
+      v.pv[2 * (size_t)i] = pa;
     }
     V4<R> rm;
     rm.x = rho;
