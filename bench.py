@@ -46,6 +46,11 @@ PEAK_HBM_GBS = 8000.0
 FLOPS_FORCE_PAIR = 58
 FLOPS_DENSITY_PAIR = 28
 FLOPS_EXTRAP_PAIR = 46
+#   neighbour search (Sec. "Parallelization via spatial decomposition":
+#   cells of edge r_c, every particle of the 27 surrounding cells is a
+#   candidate): one distance test = 3 subtractions, 3 multiplications,
+#   2 additions -> 8
+FLOPS_CANDIDATE = 8
 
 
 def parse():
@@ -67,13 +72,14 @@ def parse():
     return ap.parse_args()
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "forces_traffic_3d_column_64_spheres.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic_3d_column_64_spheres.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2103_07925_amd", "csrc", "sph_kernels.hip")
 
 
-def measured_traffic():
-    """HBM bytes per force-kernel launch from the committed counter summary,
-    or None when the kernel source has changed since the counters were taken."""
+def measured_traffic(kernel):
+    """Memory traffic per launch of `kernel` ("build" or "forces") from the
+    committed counter summary, or None when the kernel source has changed
+    since the counters were taken."""
     import hashlib
     import re
     try:
@@ -81,12 +87,28 @@ def measured_traffic():
     except OSError:
         return None
     m = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", txt)
-    b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    b = re.search(r"traffic_bytes_per_launch_%s:\s*([0-9.eE+]+)" % kernel, txt)
     if not m or not b:
         return None
     if hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest() != m.group(1):
         return None
     return float(b.group(1))
+
+
+def candidate_tests(cell_of_id, grid):
+    """Distance tests of the cell-list search: every particle tests every
+    other particle of the 27 (9 in 2D) cells around its own."""
+    nx, ny, nz = (int(grid[0]), int(grid[1]), max(int(grid[2]), 1))
+    cnt = np.bincount(np.asarray(cell_of_id, np.int64), minlength=nx * ny * nz).astype(np.int64)
+    c3 = cnt.reshape(nz, ny, nx)
+    pad = np.pad(c3, 1)
+    box = np.zeros_like(c3)
+    dzs = (-1, 0, 1) if nz > 1 else (0,)
+    for dz in dzs:
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                box += pad[1 + dz:1 + dz + nz, 1 + dy:1 + dy + ny, 1 + dx:1 + dx + nx]
+    return int(np.sum(c3 * box) - cnt.sum())
 
 
 def serving_run(n_scenes, seed):
@@ -218,10 +240,18 @@ def main():
     nrec = max(tm["steps"], 1)
     step_ms = tm["step_ms"]
     forces_ms = tm["forces"] / nrec
+    build_ms = tm["density"] / nrec
     # pairs the force kernel evaluates per launch: all neighbours of fluid
     # particles plus the fluid neighbours of rigid particles
     force_pairs = st.pairs_fluid + st.pairs_rigid
     achieved_tflops = force_pairs * FLOPS_FORCE_PAIR / (forces_ms * 1e-3) / 1e12
+    # the list build: the cell-list distance tests of every particle and the
+    # density sum of every fluid particle (its own W(0) included)
+    _, cell_of_id = g.cell_order()
+    cand = candidate_tests(cell_of_id, st.grid)
+    dens_terms = st.pairs_fluid + counts["fluid"]
+    build_flops = cand * FLOPS_CANDIDATE + dens_terms * FLOPS_DENSITY_PAIR
+    build_tflops = build_flops / (build_ms * 1e-3) / 1e12
     stage_avg = {k: tm[k] / nrec for k in B.SphScene.STAGES}
     g.sph_scene_enable_timers(False)
     del g
@@ -261,23 +291,43 @@ def main():
             "n_rigid": counts["rigid"], "n_bodies": counts["bodies"], "dx": sc.dx,
             "pairs_per_step": int(st.pairs_last), "seed": args.seed,
         },
-        "roofline": {
-            "bound": "alu",
-            "kernel": "forces (momentum + coupling + contact gather)",
-            "achieved": achieved_tflops,
-            "peak": PEAK_FP32_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved_tflops / PEAK_FP32_TFLOPS,
-            "traffic": measured_traffic(),
-            "pairs_per_launch": int(force_pairs),
-            "flops_per_pair": FLOPS_FORCE_PAIR,
-            "avg_launch_ms": forces_ms,
+        "roofline": None,   # the kernel of the two below with the longer launches
+        "rooflines": {
+            "build": {
+                "bound": "alu",
+                "kernel": "list build + density + EOS (k_build_density)",
+                "achieved": build_tflops,
+                "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s",
+                "frac": build_tflops / PEAK_FP32_TFLOPS,
+                "traffic": measured_traffic("build"),
+                "candidate_tests_per_launch": cand,
+                "flops_per_candidate": FLOPS_CANDIDATE,
+                "density_terms_per_launch": int(dens_terms),
+                "flops_per_density_term": FLOPS_DENSITY_PAIR,
+                "avg_launch_ms": build_ms,
+            },
+            "forces": {
+                "bound": "alu",
+                "kernel": "forces (momentum + coupling + contact gather, k_forces_list)",
+                "achieved": achieved_tflops,
+                "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s",
+                "frac": achieved_tflops / PEAK_FP32_TFLOPS,
+                "traffic": measured_traffic("forces"),
+                "pairs_per_launch": int(force_pairs),
+                "flops_per_pair": FLOPS_FORCE_PAIR,
+                "avg_launch_ms": forces_ms,
+            },
         },
         "stage_ms_per_step": stage_avg,
         "step_latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
         "fp64_path": {"value": value64, "unit": UNIT, "steps": args.fp64_steps,
                       "fp32_speedup": value / value64},
     }
+
+    dom = "build" if build_ms >= forces_ms else "forces"
+    out["roofline"] = dict(out["rooflines"][dom])
 
     if args.other_steps > 0:
         tv = S.config_c2(seed=args.seed)
