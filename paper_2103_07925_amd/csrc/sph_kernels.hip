@@ -741,6 +741,18 @@ __device__ __forceinline__ R dist2(const V4<R>& T, const V4<R>& s, R& d0, R& d1,
   return r2;
 }
 
+// 2 m + (r2 < rc2): in FP32 one compare into VCC and one add with carry
+// (the compiler otherwise spends a select, a shift and an or per bit)
+__device__ __forceinline__ uint32_t push_hit(uint32_t m, float r2, float rc2) {
+  uint32_t out;
+  asm("v_cmp_gt_f32 vcc, %2, %1\n\tv_addc_co_u32 %0, vcc, %3, %3, vcc"
+      : "=v"(out) : "v"(r2), "s"(rc2), "v"(m) : "vcc");
+  return out;
+}
+__device__ __forceinline__ uint32_t push_hit(uint32_t m, double r2, double rc2) {
+  return m + m + (r2 < rc2 ? 1u : 0u);
+}
+
 // maximum over the wave, returned as a wave-uniform (scalar) value so that
 // loops bounded by it are controlled by scalar instructions
 __device__ __forceinline__ int wave_max_i(int x) {
@@ -949,7 +961,7 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
   // the lane's own cells of every stencil row: cx - 1 .. cx + 1
   const int cxl = active ? (int)(v.cell[i] - wi.row * (uint32_t)nx) : g.cx_first;
   const int ca = cxl - 1 < 0 ? 0 : cxl - 1, cb = cxl + 1 > nx - 1 ? nx - 1 : cxl + 1;
-  uint16_t* gl = v.nb.ent + (size_t)w * CAP * 64 + lane;
+  uint16_t* glw = v.nb.ent + (size_t)w * CAP * 64;
   int nf = 0, nb = 0;
   bool overflow = false;
   R sum = R(0);
@@ -1015,7 +1027,7 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
         for (int u = 0; u < 32; ++u) {
           R e0, e1, e2;
           const R a0 = dist2<R, DIM>(V4<R>{T0, T1, T2, R(0)}, sp[u], e0, e1, e2);
-          m = m + m + (a0 < k.rc2 ? 1u : 0u);
+          m = push_hit(m, a0, k.rc2);
         }
         msk[wd * 64 + lane] = m;
       }
@@ -1032,16 +1044,17 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
           m &= ~(0x80000000u >> bit);
           const int q = qs + 32 * wd + bit;
           const V4<R> sj = stg[q];
-          if (dens) {
-            R d0, d1, d2;
-            const R r2 = dist2<R, DIM>(T, sj, d0, d1, d2);
-            sum = sum + kern_w<R>(ksqrt(r2), k);
-          }
+          R d0, d1, d2;
+          const R r2 = dist2<R, DIM>(T, sj, d0, d1, d2);
+          const R wk = kern_w<R>(ksqrt(r2), k);
+          sum = dens ? sum + wk : sum;
           const bool room = nf + nb < CAP;
           overflow = overflow || !room;
           const bool front = !part || ikind(r_to_info(sj.w)) == KF;
-          const int at = front ? nf : CAP - 1 - nb;
-          if (room) gl[(size_t)at * 64] = (uint16_t)(tag + (uint32_t)q);
+          // a full list (an error) keeps its slots: the entry lands on one of them
+          int at = front ? nf : CAP - 1 - nb;
+          at = at < 0 ? 0 : (at > CAP - 1 ? CAP - 1 : at);
+          glw[(uint32_t)at * 64u + (uint32_t)lane] = (uint16_t)(tag + (uint32_t)q);
           nf += (room && front) ? 1 : 0;
           nb += (room && !front) ? 1 : 0;
         }
