@@ -167,12 +167,12 @@ struct View {
   V4<R>* uw;
   R* dTdt;
   V4<R>* ab;   // transport-velocity formulation: background-pressure acceleration
-  V4<R>* rm;   // neighbour record: (rho, m, info bits, T)
+  V4<R>* rm;   // FP32 neighbour record of thermal scenes: (rho, m, info bits, T)
   V4<R>* pv;   // neighbour records, interleaved so that one neighbour's two
-               // records share a cache line: [2 j] the FP32 position record
-               // (cell offsets x, y, z and packed cell x | kind << 16 |
-               // phase << 18), [2 j + 1] (u, p) of fluid, (u~_w, p_w) of
-               // wall / rigid particles
+               // records share a cache line: [2 j] in FP32 the position
+               // record (cell offsets x, y, z and packed cell x | kind << 16 |
+               // phase << 18), in FP64 (rho, m, info bits, T); [2 j + 1]
+               // (u, p) of fluid, (u~_w, p_w) of wall / rigid particles
   // cells
   uint32_t* cstart;   // C + 1
   // rigid slots (body-sorted)

@@ -773,11 +773,12 @@ __device__ __forceinline__ int wave_max_i(int x) {
 // the neighbouring waves).  Lanes go through their own count, so lanes of a
 // wave finish together whatever part of their neighbourhood lies in which
 // stencil row.
-// FP32 sweeps without heat read two 16-byte records per neighbour: pa
-// (cell offsets, packed cell x / kind / phase) and vp; a fluid neighbour's
-// density is recovered from its pressure by the inverse equation of state
-// and its mass is that of its phase, unless a flag says otherwise (a phase
-// switch kept the old mass), in which case its full rm record is read.
+// FP32 sweeps without heat read two 16-byte records per neighbour, one
+// 32-byte pair: pa (cell offsets, packed cell x / kind / phase) and vp; a
+// fluid neighbour's density is recovered from its pressure by the inverse
+// equation of state and its mass is that of its phase.  FP32 sweeps with
+// heat add the neighbour's rm record (density, mass, temperature); FP64
+// sweeps read the position and the pair (rm, vp).
 // The walk is software-pipelined: while neighbour q is evaluated, the
 // records of q + 1 and the list entry of q + 2 are in flight.
 template <typename R>
@@ -821,8 +822,12 @@ __device__ __forceinline__ void for_list(const View<R>& v, const KC<R>& k, const
     if constexpr (PK) {
       r.a = v.pv[2 * (size_t)j];
       r.vp = v.pv[2 * (size_t)j + 1];
-    } else {
+    } else if constexpr (IsExact<R>::v) {
       r.a = v.pos[j];
+      r.rm = v.pv[2 * (size_t)j];
+      r.vp = v.pv[2 * (size_t)j + 1];
+    } else {
+      r.a = v.pv[2 * (size_t)j];
       r.vp = v.pv[2 * (size_t)j + 1];
       r.rm = v.rm[j];
     }
@@ -864,8 +869,15 @@ __device__ __forceinline__ void for_list(const View<R>& v, const KC<R>& k, const
           nb.rm.y = M.mass;
           nb.rm.z = info_to_r(mkinfo(kj, ph, 0u, -1), R(0));
           nb.rm.w = R(0);
-        } else {
+        } else if constexpr (IsExact<R>::v) {
           pj = r0.a;
+          nb.rm = r0.rm;
+        } else {
+          const uint32_t pk = __float_as_uint(r0.a.w);
+          pj.x = r0.a.x;
+          pj.y = r0.a.y;
+          pj.z = r0.a.z;
+          pj.w = (R)(pk & 0xffffu);
           nb.rm = r0.rm;
         }
         V4<R> sj;
@@ -1112,7 +1124,10 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
     rm.y = v.m[i];
     rm.z = info_to_r(inf, R(0));
     rm.w = P.thermal ? v.T[i] : R(0);
-    v.rm[i] = rm;
+    // FP64 walks read it beside (u, p); FP32 walks of thermal scenes from
+    // its own array (the others derive density and mass from the phase)
+    if constexpr (IsExact<R>::v) v.pv[2 * (size_t)i] = rm;
+    else if (P.thermal) v.rm[i] = rm;
   }
   block_add_pairs(v.pairs, pairs, 2, w);
 }
