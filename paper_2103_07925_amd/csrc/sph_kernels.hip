@@ -45,6 +45,26 @@ __device__ __forceinline__ R kern_w(R r, const KC<R>& k) {
     return w * k.wnorm;
   }
 }
+// W with the normalisation passed in (in FP64 the same arithmetic as kern_w
+// when norm is k.wnorm; in FP32 the distances to the spline knots are fused)
+template <typename R>
+__device__ __forceinline__ R kern_w_norm(R r, const KC<R>& k, R norm) {
+  if constexpr (IsExact<R>::v) {
+    R q = r / k.h;
+    if (!(q < R(3))) return R(0);
+    R w = p5(R(3) - q);
+    if (q < R(2)) w = w - R(6) * p5(R(2) - q);
+    if (q < R(1)) w = w + R(15) * p5(R(1) - q);
+    return w * norm;
+  } else {
+    // n - r / h in one rounding each
+    const R mr = -r;
+    R s3 = fmaxf(kfma(mr, k.inv_h, R(3)), R(0)), s2 = fmaxf(kfma(mr, k.inv_h, R(2)), R(0));
+    R s1 = fmaxf(kfma(mr, k.inv_h, R(1)), R(0));
+    R w = kfma(R(15), p5(s1), kfma(R(-6), p5(s2), p5(s3)));
+    return w * norm;
+  }
+}
 template <typename R>
 __device__ __forceinline__ R kern_dw(R r, const KC<R>& k) {
   if constexpr (IsExact<R>::v) {
@@ -973,9 +993,16 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
   // the lane's own cells of every stencil row: cx - 1 .. cx + 1
   const int cxl = active ? (int)(v.cell[i] - wi.row * (uint32_t)nx) : g.cx_first;
   const int ca = cxl - 1 < 0 ? 0 : cxl - 1, cb = cxl + 1 > nx - 1 ? nx - 1 : cxl + 1;
-  uint16_t* glw = v.nb.ent + (size_t)w * CAP * 64;
-  int nf = 0, nb = 0;
+  char* glw = (char*)(v.nb.ent + (size_t)w * CAP * 64);
+  // the lane's next front and back slots in its wave's list block (byte
+  // offsets: entry q of lane l at 2 (q * 64 + l)); a list with more hits
+  // than slots (an error) has its slots overwritten, every one with a
+  // valid entry, and is cut to its capacity below
+  const int lo2 = 2 * lane, hi2 = 2 * ((CAP - 1) * 64 + lane);
+  int fo = lo2, bo = hi2;
   bool overflow = false;
+  // W's normalisation for the lanes that sum a density, zero for the others
+  const R wsig = dens ? k.wnorm : R(0);
   R sum = R(0);
   for (int rr = 0; rr < NR; ++rr) {
     const int dz = DIM == 3 ? rr / 3 - 1 : 0, dy = rr % 3 - 1;
@@ -1007,7 +1034,7 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
             sq.y = sq.y + shy;
             sq.z = sq.z + shz;
           }
-          sq.w = info_to_r(v.info[seg + q], R(0));
+          sq.w = ikind(v.info[seg + q]) == KF ? R(0) : R(-1);   // non-fluid: < 0
         } else {
           sq.x = sq.y = sq.z = -far;    // padding: never a neighbour
           sq.w = R(0);
@@ -1030,7 +1057,7 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
       }
       const int mlen = wave_max_i(qb - qa);
       const int qs = qa < ns - mlen ? qa : ns - mlen;
-      const int nwd = (mlen + 31) >> 5;
+      const int nwd = (mlen + 31) >> 5, wlast = nwd - 1;
       // candidate tests: bit 31 - u of word wd is candidate qs + 32 wd + u
       for (int wd = 0; wd < nwd; ++wd) {
         const V4<R>* sp = stg + qs + 32 * wd;
@@ -1047,36 +1074,38 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
       // Every lane walks its own hits across all words of the segment, so
       // the wave loops max-over-lanes of the segment's hits (not the sum
       // over words of each word's maximum)
+      // the current word: its mask, its first candidate, that candidate's entry
       int wd = 0;
       uint32_t m = nwd > 0 ? msk[lane] : 0u;
-      while (m == 0u && wd + 1 < nwd) m = msk[++wd * 64 + lane];
+      while (m == 0u && wd < wlast) m = msk[++wd * 64 + lane];
+      const V4<R>* sw = stg + qs + 32 * wd;
+      uint32_t tw = tag + (uint32_t)(qs + 32 * wd);
       while (m != 0u) {
-        {
-          const int bit = __builtin_clz(m);
-          m &= ~(0x80000000u >> bit);
-          const int q = qs + 32 * wd + bit;
-          const V4<R> sj = stg[q];
-          R d0, d1, d2;
-          const R r2 = dist2<R, DIM>(T, sj, d0, d1, d2);
-          const R wk = kern_w<R>(ksqrt(r2), k);
-          sum = dens ? sum + wk : sum;
-          const bool room = nf + nb < CAP;
-          overflow = overflow || !room;
-          const bool front = !part || ikind(r_to_info(sj.w)) == KF;
-          // a full list (an error) keeps its slots: the entry lands on one of them
-          int at = front ? nf : CAP - 1 - nb;
-          at = at < 0 ? 0 : (at > CAP - 1 ? CAP - 1 : at);
-          glw[(uint32_t)at * 64u + (uint32_t)lane] = (uint16_t)(tag + (uint32_t)q);
-          nf += (room && front) ? 1 : 0;
-          nb += (room && !front) ? 1 : 0;
+        const int bit = __builtin_clz(m);
+        m &= ~(0x80000000u >> bit);
+        const V4<R> sj = sw[bit];
+        R d0, d1, d2;
+        const R r2 = dist2<R, DIM>(T, sj, d0, d1, d2);
+        sum = sum + kern_w_norm<R>(ksqrt(r2), k, wsig);
+        const bool front = !part || !(sj.w < R(0));
+        const int at = min(max(front ? fo : bo, lo2), hi2);
+        *(uint16_t*)(glw + (uint32_t)at) = (uint16_t)(tw + (uint32_t)bit);
+        fo += front ? 128 : 0;
+        bo -= front ? 0 : 128;
+        while (m == 0u && wd < wlast) {
+          m = msk[++wd * 64 + lane];
+          sw += 32;
+          tw += 32u;
         }
-        while (m == 0u && wd + 1 < nwd) m = msk[++wd * 64 + lane];
       }
       __syncthreads();
     }
   }
+  const int nhf = (fo - lo2) >> 7, nhb = (hi2 - bo) >> 7;   // hits, front and back
+  overflow = overflow || nhf + nhb > CAP;
   if (overflow && active) set_err(v.err, ERR_NBCAP);
-  const int cnt = active ? nf + nb : 0;
+  const int nf = nhf < CAP ? nhf : CAP;
+  const int cnt = active ? (nhf + nhb < CAP ? nhf + nhb : CAP) : 0;
   v.nb.cnt[(size_t)w * 64 + lane] = (uint8_t)cnt;
   // wall and rigid lanes join the compact extrapolation list
   const unsigned long long pm = __ballot(part);

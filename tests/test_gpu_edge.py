@@ -89,6 +89,20 @@ def test_escape_is_a_sticky_error(B):
     assert g.stats().device_error & 1
 
 
+def test_neighbour_capacity_is_a_sticky_error(B):
+    """A fluid block packed at half its lattice spacing gives interior
+    particles about eight times the lattice neighbours, beyond the list
+    capacity (191 and the particle itself): the set-up evaluation finishes
+    with every entry inside the particle's list block and reports the
+    capacity bit, so the scene is not created."""
+    sc = S.fluid_box(dim=3, n_side=14, walls=False)
+    c = sc.x.mean(axis=0)
+    sc.x = np.ascontiguousarray(c + 0.5 * (sc.x - c))
+    for prec in (B.SPH_FP32_SWEEP, B.SPH_FP64):
+        with pytest.raises(RuntimeError, match="set-up: 32"):
+            B.SphScene(sc, precision=prec, dt=1e-6)
+
+
 def test_fp32_thermal_switching_gates(B):
     """FP32 sweep with conduction and phase switching (temperatures kept away
     from T_t, so the switching decisions are the oracle's)."""
