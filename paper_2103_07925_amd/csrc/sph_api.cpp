@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/sphrb.h"
@@ -86,7 +87,7 @@ struct sph_scene {
   int32_t* aux[2];
   int ip, iu, iT;
   void* ud[2];       // transport-velocity formulation: u~ - u (permuted with pos)
-  void *rho, *p, *pw, *uw, *dTdt, *pv, *rm, *ab;
+  void *rho, *p, *pw, *uw, *dTdt, *pv, *ab;
   SortBufs sb;
   uint32_t* cstart;
   V4<double> *s_rb, *s_rk, *s_f, *s_aw, *s_x;
@@ -274,8 +275,7 @@ void carve(Carver& cv, sph_scene* s, const Params& P, int64_t nmat) {
   s->pw = cv.take<R>(n);
   s->uw = cv.take<V4<R>>(n);
   s->dTdt = cv.take<R>(n);
-  s->pv = cv.take<V4<R>>(2 * n);
-  s->rm = cv.take<V4<R>>(n);
+  s->pv = cv.take<V4<R>>((size_t)rec_stride(std::is_same<R, double>::value, P.thermal != 0, P.tvf != 0) * n);
   s->sb.key = cv.take<uint32_t>(n);
   s->sb.rank = cv.take<uint32_t>(n);
   s->sb.tid = cv.take<uint32_t>(n);
@@ -488,7 +488,7 @@ View<R> make_view(sph_scene* s, int ip, int iu, int iT) {
   v.uw = (V4<R>*)s->uw;
   v.dTdt = (R*)s->dTdt;
   v.pv = (V4<R>*)s->pv;
-  v.rm = (V4<R>*)s->rm;
+  v.pvs = rec_stride(std::is_same<R, double>::value, s->P.thermal != 0, s->P.tvf != 0);
   v.cstart = s->cstart;
   v.s_rb = s->s_rb;
   v.s_rk = s->s_rk;

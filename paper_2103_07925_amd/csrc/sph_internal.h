@@ -144,6 +144,16 @@ struct PhaseBufs {
 };
 
 // device pointers of one scene
+// Neighbour records per particle, written every step by the list build:
+// FP32 [pa, vp] (pa: cell offsets x, y, z and packed cell x | kind << 16 |
+// phase << 18), then rm with heat; FP64 [rm, vp]; then a copy of u~ - u
+// with the transport-velocity option.  vp = (u, p) of fluid, (u~_w, p_w)
+// of wall and rigid particles; rm = (rho, m, info bits, T).
+__host__ __device__ constexpr int rec_stride(bool fp64, bool thermal, bool tvf) {
+  return 2 + ((!fp64 && thermal) ? 1 : 0) + (tvf ? 1 : 0);
+}
+__host__ __device__ constexpr int rec_rm_slot(bool fp64) { return fp64 ? 0 : 2; }
+
 template <typename R>
 struct View {
   // sorted, permuted state (current buffers)
@@ -167,12 +177,9 @@ struct View {
   V4<R>* uw;
   R* dTdt;
   V4<R>* ab;   // transport-velocity formulation: background-pressure acceleration
-  V4<R>* rm;   // FP32 neighbour record of thermal scenes: (rho, m, info bits, T)
-  V4<R>* pv;   // neighbour records, interleaved so that one neighbour's two
-               // records share a cache line: [2 j] in FP32 the position
-               // record (cell offsets x, y, z and packed cell x | kind << 16 |
-               // phase << 18), in FP64 (rho, m, info bits, T); [2 j + 1]
-               // (u, p) of fluid, (u~_w, p_w) of wall / rigid particles
+  V4<R>* pv;   // neighbour records, pvs per particle side by side so that
+               // one neighbour's records share cache lines (rec_stride)
+  int32_t pvs;
   // cells
   uint32_t* cstart;   // C + 1
   // rigid slots (body-sorted)
@@ -218,7 +225,7 @@ struct Slot {
 template <typename R, typename F>
 __host__ __device__ inline void for_each_ptr(View<R>& v, F&& f) {
   f(v.pos); f(v.cell); f(v.u); f(v.a); f(v.T); f(v.m); f(v.id); f(v.info); f(v.aux); f(v.ud);
-  f(v.u_out); f(v.T_out); f(v.rho); f(v.p); f(v.pw); f(v.uw); f(v.dTdt); f(v.ab); f(v.pv); f(v.rm);
+  f(v.u_out); f(v.T_out); f(v.rho); f(v.p); f(v.pw); f(v.uw); f(v.dTdt); f(v.ab); f(v.pv);
   f(v.cstart); f(v.s_rb); f(v.s_rk); f(v.s_f); f(v.s_aw); f(v.s_x); f(v.s_m); f(v.s_sorted); f(v.s_body);
   f(v.s_id); f(v.w_x0); f(v.w_aw); f(v.w_sorted); f(v.mat); f(v.bodies); f(v.err); f(v.pairs);
   f(v.nb.table); f(v.nb.nwaves); f(v.nb.ent); f(v.nb.cnt); f(v.nb.split); f(v.nb.ext); f(v.nb.ext_n);

@@ -262,6 +262,7 @@ struct Nbr {
   uint32_t j;
   V4<R> vp;
   V4<R> rm;
+  V4<R> ud;   // u~ - u (transport-velocity walks only)
 };
 
 __device__ __forceinline__ float info_to_r(uint32_t v, float) { return __uint_as_float(v); }
@@ -380,7 +381,7 @@ __device__ __forceinline__ uint32_t extrap_one(const View<R>& v, const KC<R>& k,
   o.w = pw;
   v.pw[i] = pw;
   v.uw[i] = o;
-  v.pv[2 * (size_t)i + 1] = o;
+  v.pv[(size_t)v.pvs * i + 1] = o;
   if (kind == KR) v.p[i] = pw;
   return c;
 }
@@ -523,7 +524,7 @@ __device__ __forceinline__ void forces_one(const View<R>& v, const Params& P, co
   const R p_i = v.p[i];
   const R eta_i = Mi.eta;
   const R ka = Mi.kappa;
-  const V4<R> vpr = v.pv[2 * (size_t)i + 1];
+  const V4<R> vpr = v.pv[(size_t)rec_stride(IsExact<R>::v, THERMAL, TVF) * i + 1];
   const R pw_r = vpr.w;
   const int body_i = ibody(inf);
   V4<R> udi;
@@ -559,7 +560,7 @@ __device__ __forceinline__ void forces_one(const View<R>& v, const Params& P, co
       pair_force<R, DIM>(rA, pA, mA, eA, uA0, uA1, uA2, rB, nb.vp.w, mB, eB, nb.vp.x, nb.vp.y, nb.vp.z, d0, d1, d2,
                          r, dW, F, c);
       if constexpr (TVF) {
-        if (fluid && fj) pair_stress<R, DIM>(c, rho_i, ui, udi, nb.rm.x, nb.vp.x, nb.vp.y, nb.vp.z, v.ud[nb.j], d0, d1,
+        if (fluid && fj) pair_stress<R, DIM>(c, rho_i, ui, udi, nb.rm.x, nb.vp.x, nb.vp.y, nb.vp.z, nb.ud, d0, d1,
                                              d2, F);
         if constexpr (IsExact<R>::v) {
           bs0 = bs0 + c * d0;
@@ -798,12 +799,14 @@ __device__ __forceinline__ int wave_max_i(int x) {
 // fluid neighbour's density is recovered from its pressure by the inverse
 // equation of state and its mass is that of its phase.  FP32 sweeps with
 // heat add the neighbour's rm record (density, mass, temperature); FP64
-// sweeps read the position and the pair (rm, vp).
+// sweeps read the position and the pair (rm, vp); transport-velocity force
+// sweeps add the neighbour's u~ - u.  A particle's records sit side by side
+// (S per particle, rec_stride), so they share cache lines.
 // The walk is software-pipelined: while neighbour q is evaluated, the
 // records of q + 1 and the list entry of q + 2 are in flight.
 template <typename R>
 struct NbRec {
-  V4<R> a, vp, rm;
+  V4<R> a, vp, rm, ud;
 };
 
 // gl: the lane's column of its wave's list block; jl: the stencil-row bases
@@ -821,11 +824,11 @@ __device__ __forceinline__ void stage_rows(R* ro, const KC<R>& k) {
   }
 }
 
-template <typename R, int DIM, bool PACKED, typename F>
+template <typename R, int DIM, bool PACKED, bool UD, typename F>
 __device__ __forceinline__ void for_list(const View<R>& v, const KC<R>& k, const MatL<R>* sm, const R* ro,
                                          int cx_first, uint64_t wc, const uint32_t* jl, const uint16_t* gl,
-                                         int n_all, int split, uint32_t i, const V4<R>& T, bool with_self,
-                                         F&& visit, int q0 = 0, int dq = 1) {
+                                         int S, int n_all, int split, uint32_t i, const V4<R>& T,
+                                         bool with_self, F&& visit, int q0 = 0, int dq = 1) {
   constexpr int CAP = Nb<DIM>::cap;
   constexpr bool PK = PACKED && !IsExact<R>::v;
   const int n_lane = n_all > q0 ? (n_all - q0 + dq - 1) / dq : 0;   // this lane's entries
@@ -839,18 +842,20 @@ __device__ __forceinline__ void for_list(const View<R>& v, const KC<R>& k, const
   auto index = [&](uint32_t e) -> uint32_t { return jl[e >> 12] + (e & 0xfffu); };
   auto fetch = [&](uint32_t e, NbRec<R>& r) {
     const uint32_t j = index(e);
+    const V4<R>* rec = v.pv + (uint32_t)S * j;   // below 2^32 records: the arena is smaller
     if constexpr (PK) {
-      r.a = v.pv[2 * (size_t)j];
-      r.vp = v.pv[2 * (size_t)j + 1];
+      r.a = rec[0];
+      r.vp = rec[1];
     } else if constexpr (IsExact<R>::v) {
       r.a = v.pos[j];
-      r.rm = v.pv[2 * (size_t)j];
-      r.vp = v.pv[2 * (size_t)j + 1];
+      r.rm = rec[rec_rm_slot(true)];
+      r.vp = rec[1];
     } else {
-      r.a = v.pv[2 * (size_t)j];
-      r.vp = v.pv[2 * (size_t)j + 1];
-      r.rm = v.rm[j];
+      r.a = rec[0];
+      r.vp = rec[1];
+      r.rm = rec[rec_rm_slot(false)];
     }
+    if constexpr (UD) r.ud = rec[S - 1];
   };
   uint32_t e0 = 0u, e1 = 0u;
   NbRec<R> r0;
@@ -871,6 +876,7 @@ __device__ __forceinline__ void for_list(const View<R>& v, const KC<R>& k, const
         Nbr<R> nb;
         nb.j = j;
         nb.vp = r0.vp;
+        if constexpr (UD) nb.ud = r0.ud;
         V4<R> pj;
         if constexpr (PK) {
           const uint32_t pk = __float_as_uint(r0.a.w);
@@ -1131,7 +1137,7 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
       v.p[i] = p;
       V4<R> vp = v.u[i];
       vp.w = p;
-      v.pv[2 * (size_t)i + 1] = vp;
+      v.pv[(size_t)v.pvs * i + 1] = vp;
       pairs = (unsigned long long)(cnt - 1);
     } else {
       rho = kind == KR ? M.rho0 : R(0);
@@ -1146,17 +1152,17 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
       pa.y = po.y;
       pa.z = po.z;
       pa.w = __uint_as_float(pk);
-      v.pv[2 * (size_t)i] = pa;
+      v.pv[(size_t)v.pvs * i] = pa;
     }
     V4<R> rm;
     rm.x = rho;
     rm.y = v.m[i];
     rm.z = info_to_r(inf, R(0));
     rm.w = P.thermal ? v.T[i] : R(0);
-    // FP64 walks read it beside (u, p); FP32 walks of thermal scenes from
-    // its own array (the others derive density and mass from the phase)
-    if constexpr (IsExact<R>::v) v.pv[2 * (size_t)i] = rm;
-    else if (P.thermal) v.rm[i] = rm;
+    // FP32 walks without heat derive density and mass from the phase
+    if (IsExact<R>::v || P.thermal) v.pv[(size_t)v.pvs * i + rec_rm_slot(IsExact<R>::v)] = rm;
+    // the transport-velocity walks read a neighbour's u~ - u beside its records
+    if (P.tvf) v.pv[(size_t)v.pvs * i + v.pvs - 1] = v.ud[i];
   }
   block_add_pairs(v.pairs, pairs, 2, w);
 }
@@ -1201,9 +1207,9 @@ __device__ __forceinline__ void extrapolate_wave(const View<R>& v, const Params&
     const int n_f = need ? (int)v.nb.split[(size_t)w * 64 + l] : 0;
     unsigned long long cr = 0, cw = 0;
     const uint32_t c = extrap_one<R, DIM, kExtSub>(v, k, smat, i, need, sub == 0, [&](bool ws, auto&& f) {
-      for_list<R, DIM, true>(v, k, smat, ro, g.cx_first, wrap_codes<DIM>(P, g.cy, g.cz), jls + lane * NR,
-                             v.nb.ent + (size_t)w * CAP * 64 + l, n_f,
-                             n_f, i, T, ws, f, sub, kExtSub);
+      for_list<R, DIM, true, false>(v, k, smat, ro, g.cx_first, wrap_codes<DIM>(P, g.cy, g.cz), jls + lane * NR,
+                                    v.nb.ent + (size_t)w * CAP * 64 + l, v.pvs, n_f,
+                                    n_f, i, T, ws, f, sub, kExtSub);
     });
     if (need && sub == 0 && kind == KR) cr = c;
     else if (need && sub == 0) cw = c;
@@ -1245,9 +1251,9 @@ __device__ __forceinline__ void forces_wave(const View<R>& v, const Params& P, c
   const int split = v.nb.split[(size_t)w * 64 + lane];
   const double t = (double)(*v.dstep) * P.dt;
   forces_one<R, DIM, THERMAL, TVF>(v, P, k, smat, i, need, kick, heat, t, [&](bool ws, auto&& f) {
-    for_list<R, DIM, THERMAL == 0>(v, k, smat, ro, g.cx_first, wrap_codes<DIM>(P, g.cy, g.cz), jl,
-                                   v.nb.ent + (size_t)w * Nb<DIM>::cap * 64 + lane,
-                                   n_lane, split, i, T, ws, f);
+    for_list<R, DIM, THERMAL == 0, TVF != 0>(v, k, smat, ro, g.cx_first, wrap_codes<DIM>(P, g.cy, g.cz), jl,
+                                             v.nb.ent + (size_t)w * Nb<DIM>::cap * 64 + lane,
+                                             rec_stride(IsExact<R>::v, THERMAL, TVF), n_lane, split, i, T, ws, f);
   });
 }
 

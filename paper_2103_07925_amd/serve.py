@@ -23,6 +23,7 @@ from __future__ import annotations
 import dataclasses
 import json
 import math
+import sys
 import time
 from typing import Callable, List, Optional
 
@@ -269,11 +270,14 @@ def main():
     args = ap.parse_args()
     be = GpuBackend()
     reqs = make_requests(args.scenes, seed=args.seed, n_range=(args.n_min, args.n_max), steps=args.steps)
+    print(f"{len(reqs)} requests, {sum(r.scene.n for r in reqs)} particles", file=sys.stderr, flush=True)
     total = sum(be.footprint(r) for r in reqs)
     budget = int(args.budget_gb * 1e9) if args.budget_gb > 0 else max(total // 3, max(be.footprint(r) for r in reqs))
     # capacity: the same requests all at once (closed loop)
     cal = Server(be, budget, args.max_active).run(reqs)
     cap = len(reqs) / cal["makespan_s"]
+    print(f"closed loop: {cal['makespan_s']:.2f} s, {cal['pair_interactions_per_s']:.3g} pairs/s", file=sys.stderr,
+          flush=True)
     rate = args.load * cap
     rng = np.random.default_rng(args.seed + 1)
     t = 0.0
