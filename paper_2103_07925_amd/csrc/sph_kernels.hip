@@ -773,15 +773,6 @@ __device__ __forceinline__ uint32_t push_hit(uint32_t m, float r2, float rc2) {
 __device__ __forceinline__ uint32_t push_hit(uint32_t m, double r2, double rc2) {
   return m + m + (r2 < rc2 ? 1u : 0u);
 }
-__device__ __forceinline__ bool signbit_of(float x) { return __float_as_int(x) < 0; }
-__device__ __forceinline__ bool signbit_of(double x) { return x < 0.0; }
-// the same against a per-lane bound
-__device__ __forceinline__ uint32_t push_below(uint32_t m, float a, float bound) {
-  uint32_t out;
-  asm("v_cmp_gt_f32 vcc, %2, %1\n\tv_addc_co_u32 %0, vcc, %3, %3, vcc"
-      : "=v"(out) : "v"(a), "v"(bound), "v"(m) : "vcc");
-  return out;
-}
 
 // maximum over the wave, returned as a wave-uniform (scalar) value so that
 // loops bounded by it are controlled by scalar instructions
@@ -1002,22 +993,6 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
   // inactive lanes test against an unreachable point and never hit
   const R far = R(1e30);
   const R T0 = active ? T.x : far, T1 = active ? T.y : far, T2 = active ? T.z : far;
-  // FP32 tests in expanded form: |s|^2 - 2 T.s < rc^2 - |T|^2 + margin, with
-  // |s|^2 staged (three fused multiply-adds per candidate instead of five
-  // operations); the margin, 2^-16 M^2 for coordinates of the wave's frame
-  // bounded by M, is about ten times the rounding error of both sides, so
-  // the form keeps every pair with r^2 < rc^2 (the exact test of the walk
-  // then drops the few extra ones: the pairs are those of the plain test)
-  R m2x = R(0), m2y = R(0), m2z = R(0), thr = R(0);
-  if constexpr (!IsExact<R>::v) {
-    m2x = R(-2) * T0;
-    m2y = R(-2) * T1;
-    m2z = R(-2) * T2;
-    const R span = (R)(g.chi - g.cx_first + 2);
-    const R M2 = kfma(span, span, R(8)) * k.L * k.L;
-    const R tt = kfma(T2, T2, kfma(T1, T1, T0 * T0));
-    thr = kfma(M2, R(1.0 / 65536.0), k.rc2) - tt;
-  }
   // wall and rigid lanes keep their fluid neighbours first (in canonical
   // order), the others from the end of their block backwards
   const bool part = active && kind != KF;
@@ -1065,16 +1040,10 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
             sq.y = sq.y + shy;
             sq.z = sq.z + shz;
           }
-          // non-fluid: the sign bit (FP32: -|s|^2; FP64: -1)
-          if constexpr (IsExact<R>::v) {
-            sq.w = ikind(v.info[seg + q]) == KF ? R(0) : R(-1);
-          } else {
-            const R s2 = kfma(sq.z, sq.z, kfma(sq.y, sq.y, sq.x * sq.x));
-            sq.w = ikind(v.info[seg + q]) == KF ? s2 : -s2;
-          }
+          sq.w = ikind(v.info[seg + q]) == KF ? R(0) : R(-1);   // non-fluid: < 0
         } else {
           sq.x = sq.y = sq.z = -far;    // padding: never a neighbour
-          sq.w = IsExact<R>::v ? R(0) : R(INFINITY);
+          sq.w = R(0);
         }
         stg[q] = sq;
       }
@@ -1101,16 +1070,9 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
         uint32_t m = 0u;
 #pragma unroll 8
         for (int u = 0; u < 32; ++u) {
-          if constexpr (IsExact<R>::v) {
-            R e0, e1, e2;
-            const R a0 = dist2<R, DIM>(V4<R>{T0, T1, T2, R(0)}, sp[u], e0, e1, e2);
-            m = push_hit(m, a0, k.rc2);
-          } else {
-            const V4<R> c = sp[u];
-            R a = kfma(m2y, c.y, kfma(m2x, c.x, fabsf(c.w)));
-            if (DIM == 3) a = kfma(m2z, c.z, a);
-            m = push_below(m, a, thr);
-          }
+          R e0, e1, e2;
+          const R a0 = dist2<R, DIM>(V4<R>{T0, T1, T2, R(0)}, sp[u], e0, e1, e2);
+          m = push_hit(m, a0, k.rc2);
         }
         msk[wd * 64 + lane] = m;
       }
@@ -1130,13 +1092,12 @@ __device__ __forceinline__ void build_density_wave(const View<R>& v, const Param
         const V4<R> sj = sw[bit];
         R d0, d1, d2;
         const R r2 = dist2<R, DIM>(T, sj, d0, d1, d2);
-        const bool hit = IsExact<R>::v || r2 < k.rc2;   // FP32: the exact test
-        sum = sum + kern_w_norm<R>(ksqrt(r2), k, hit ? wsig : R(0));
-        const bool front = !part || !signbit_of(sj.w);
+        sum = sum + kern_w_norm<R>(ksqrt(r2), k, wsig);
+        const bool front = !part || !(sj.w < R(0));
         const int at = min(max(front ? fo : bo, lo2), hi2);
-        if (hit) *(uint16_t*)(glw + (uint32_t)at) = (uint16_t)(tw + (uint32_t)bit);
-        fo += (hit && front) ? 128 : 0;
-        bo -= (hit && !front) ? 128 : 0;
+        *(uint16_t*)(glw + (uint32_t)at) = (uint16_t)(tw + (uint32_t)bit);
+        fo += front ? 128 : 0;
+        bo -= front ? 0 : 128;
         while (m == 0u && wd < wlast) {
           m = msk[++wd * 64 + lane];
           sw += 32;
@@ -2288,20 +2249,27 @@ void Launch<R>::extrapolate(const View<R>& v, const Params& P, const KC<R>& k, h
   if (P.dim == 2) k_extrapolate_list<R, 2><<<g, 64, 0, st>>>(v, P, k);
   else k_extrapolate_list<R, 3><<<g, 64, 0, st>>>(v, P, k);
 }
+// unused dynamic LDS that holds the FP32 force sweep at about 3.5 waves per
+// SIMD: its gathers share the L1, and more waves only evict each other's
+// lines (0.653 ms at 8 waves per SIMD against 0.641 ms at 3.5 and 0.682 ms
+// at 2.25 on the 3D column); FP64 is held at 4 by its registers
+template <typename R>
+constexpr size_t forces_lds() { return IsExact<R>::v ? 0 : 10240; }
+
 template <typename R>
 void Launch<R>::forces(const View<R>& v, const Params& P, const KC<R>& k, int kick, int heat, hipStream_t st) {
   if (P.n <= 0) return;
   const unsigned g = (unsigned)P.max_waves;
   const int mode = (P.thermal ? 1 : 0) | (P.tvf ? 2 : 0);
   switch (mode | (P.dim == 3 ? 4 : 0)) {
-    case 0: k_forces_list<R, 2, 0, 0><<<g, 64, 0, st>>>(v, P, k, kick, heat); break;
-    case 1: k_forces_list<R, 2, 1, 0><<<g, 64, 0, st>>>(v, P, k, kick, heat); break;
-    case 2: k_forces_list<R, 2, 0, 1><<<g, 64, 0, st>>>(v, P, k, kick, heat); break;
-    case 3: k_forces_list<R, 2, 1, 1><<<g, 64, 0, st>>>(v, P, k, kick, heat); break;
-    case 4: k_forces_list<R, 3, 0, 0><<<g, 64, 0, st>>>(v, P, k, kick, heat); break;
-    case 5: k_forces_list<R, 3, 1, 0><<<g, 64, 0, st>>>(v, P, k, kick, heat); break;
-    case 6: k_forces_list<R, 3, 0, 1><<<g, 64, 0, st>>>(v, P, k, kick, heat); break;
-    default: k_forces_list<R, 3, 1, 1><<<g, 64, 0, st>>>(v, P, k, kick, heat); break;
+    case 0: k_forces_list<R, 2, 0, 0><<<g, 64, forces_lds<R>(), st>>>(v, P, k, kick, heat); break;
+    case 1: k_forces_list<R, 2, 1, 0><<<g, 64, forces_lds<R>(), st>>>(v, P, k, kick, heat); break;
+    case 2: k_forces_list<R, 2, 0, 1><<<g, 64, forces_lds<R>(), st>>>(v, P, k, kick, heat); break;
+    case 3: k_forces_list<R, 2, 1, 1><<<g, 64, forces_lds<R>(), st>>>(v, P, k, kick, heat); break;
+    case 4: k_forces_list<R, 3, 0, 0><<<g, 64, forces_lds<R>(), st>>>(v, P, k, kick, heat); break;
+    case 5: k_forces_list<R, 3, 1, 0><<<g, 64, forces_lds<R>(), st>>>(v, P, k, kick, heat); break;
+    case 6: k_forces_list<R, 3, 0, 1><<<g, 64, forces_lds<R>(), st>>>(v, P, k, kick, heat); break;
+    default: k_forces_list<R, 3, 1, 1><<<g, 64, forces_lds<R>(), st>>>(v, P, k, kick, heat); break;
   }
 }
 template <typename R>
@@ -2317,14 +2285,14 @@ void Launch<R>::batch_sweep(int stage, const Slot<R>* tab, const char* gbase, in
   } else {
     // mode: bit 0 thermal, bit 1 transport-velocity formulation
     switch ((mode & 3) | (dim == 3 ? 4 : 0)) {
-      case 0: k_forces_batch<R, 2, 0, 0><<<blocks, 64, 0, st>>>(tab, gbase, ns, kick, heat); break;
-      case 1: k_forces_batch<R, 2, 1, 0><<<blocks, 64, 0, st>>>(tab, gbase, ns, kick, heat); break;
-      case 2: k_forces_batch<R, 2, 0, 1><<<blocks, 64, 0, st>>>(tab, gbase, ns, kick, heat); break;
-      case 3: k_forces_batch<R, 2, 1, 1><<<blocks, 64, 0, st>>>(tab, gbase, ns, kick, heat); break;
-      case 4: k_forces_batch<R, 3, 0, 0><<<blocks, 64, 0, st>>>(tab, gbase, ns, kick, heat); break;
-      case 5: k_forces_batch<R, 3, 1, 0><<<blocks, 64, 0, st>>>(tab, gbase, ns, kick, heat); break;
-      case 6: k_forces_batch<R, 3, 0, 1><<<blocks, 64, 0, st>>>(tab, gbase, ns, kick, heat); break;
-      default: k_forces_batch<R, 3, 1, 1><<<blocks, 64, 0, st>>>(tab, gbase, ns, kick, heat); break;
+      case 0: k_forces_batch<R, 2, 0, 0><<<blocks, 64, forces_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
+      case 1: k_forces_batch<R, 2, 1, 0><<<blocks, 64, forces_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
+      case 2: k_forces_batch<R, 2, 0, 1><<<blocks, 64, forces_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
+      case 3: k_forces_batch<R, 2, 1, 1><<<blocks, 64, forces_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
+      case 4: k_forces_batch<R, 3, 0, 0><<<blocks, 64, forces_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
+      case 5: k_forces_batch<R, 3, 1, 0><<<blocks, 64, forces_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
+      case 6: k_forces_batch<R, 3, 0, 1><<<blocks, 64, forces_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
+      default: k_forces_batch<R, 3, 1, 1><<<blocks, 64, forces_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
     }
   }
 }
