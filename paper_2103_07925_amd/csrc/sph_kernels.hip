@@ -252,9 +252,10 @@ __device__ __forceinline__ void clear_eval_pairs(unsigned long long* pairs, int 
 // ---------------------------------------------------------------------------
 // neighbour data
 //
-// The sweeps read each neighbour through two packed records, written once
-// per step: vp = (u, p) of fluid particles and (u~_w, p_w) of wall and rigid
-// particles; rm = (rho, m, info bits, T).
+// The sweeps read each neighbour through records written once per step and
+// kept side by side per particle (rec_stride): vp = (u, p) of fluid
+// particles and (u~_w, p_w) of wall and rigid particles; rm = (rho, m, info
+// bits, T); in FP32 pa, the position record.
 // ---------------------------------------------------------------------------
 
 template <typename R>
@@ -964,15 +965,18 @@ __global__ void __launch_bounds__(256) k_row_waves_fill(const uint32_t* cstart, 
   }
 }
 
-// Candidate test and density: every stencil row's window is staged in LDS
-// (positions in the wave frame); every lane tests every candidate of the row
-// and appends its hits to a row-local list in LDS (branch-free: the entry is
-// always written, the count advances on a hit), sums W over the new entries
-// (eq. nummeth_fluid_densum, the particle itself included), and the row's
-// entries are appended to the lane's list in HBM for the extrapolation and
-// force sweeps.  The equation of state (eq. nummeth_fluid_eos) closes the
-// density; the packed neighbour records rm (all particles) and vp (fluid)
-// are written here.
+// Candidate test and density.  Per stencil row the wave stages the row's
+// candidate window in LDS (positions in the wave frame; the sign of the
+// fourth component marks a non-fluid candidate).  Every lane tests a run of
+// 32-candidate words that covers its own cells cx - 1 .. cx + 1 (a common
+// word count from a clamped start, so that loop bounds stay wave-uniform)
+// and keeps the hit masks in LDS; then it walks its hits in candidate order
+// across the words: W summed for the density (eq. nummeth_fluid_densum, the
+// particle itself included) and the entry (stencil row << 12 | offset from
+// the row's first candidate) appended to its list in HBM for the
+// extrapolation and force sweeps.  The equation of state (eq.
+// nummeth_fluid_eos) closes the density; the particle's neighbour records
+// in pv are written here.
 
 template <typename R, int DIM>
 __device__ __forceinline__ void build_density_wave(const View<R>& v, const Params& P, const KC<R>& k, int w) {
