@@ -1227,14 +1227,14 @@ __global__ void __launch_bounds__(64) k_extrapolate_list(View<R> v, Params P, KC
   extrapolate_wave<R, DIM>(v, P, k, (int)blockIdx.x, (int)gridDim.x);
 }
 
+// one wave's force sweep (wave w, lane lane); the material table, the row
+// offsets and the wave's stencil-row bases are staged by the caller.
 // t = (steps begun) x dt, from the scene's device step counter
 template <typename R, int DIM, int THERMAL, int TVF>
-__device__ __forceinline__ void forces_wave(const View<R>& v, const Params& P, const KC<R>& k, int w, int kick,
-                                            int heat) {
-  __shared__ uint32_t jl[Nb<DIM>::rows];
-  if (w >= (int)*v.nb.nwaves) return;
+__device__ __forceinline__ void forces_wave_body(const View<R>& v, const Params& P, const KC<R>& k, int w,
+                                                 int lane, const MatL<R>* smat, const R* ro, const uint32_t* jl,
+                                                 int kick, int heat) {
   const WaveInfo wi = v.nb.table[w];
-  const int lane = threadIdx.x;
   const bool active = lane < (int)wi.cnt;
   const uint32_t i = wi.p0 + (active ? (uint32_t)lane : 0u);
   const uint32_t kind = ikind(v.info[i]);
@@ -1245,11 +1245,6 @@ __device__ __forceinline__ void forces_wave(const View<R>& v, const Params& P, c
   }
   const bool need = active && kind != KW;
   if (!__any(need)) return;
-  __shared__ MatL<R> smat[kMatLds];
-  __shared__ R ro[2 * Nb<DIM>::rows];
-  stage_rows<R, DIM>(ro, k);
-  stage_mats<R>(smat, v, P);
-  stage_jlo<DIM>(jl, v.nb, w);
   const V4<R> T = to_frame<R>(v.pos[i], k, g.cx_first, 0, 0);
   const int n_lane = need ? (int)v.nb.cnt[(size_t)w * 64 + lane] : 0;
   const int split = v.nb.split[(size_t)w * 64 + lane];
@@ -1261,9 +1256,44 @@ __device__ __forceinline__ void forces_wave(const View<R>& v, const Params& P, c
   });
 }
 
+// one wave per workgroup (the batched sweep)
 template <typename R, int DIM, int THERMAL, int TVF>
-__global__ void __launch_bounds__(64) k_forces_list(View<R> v, Params P, KC<R> k, int kick, int heat) {
-  forces_wave<R, DIM, THERMAL, TVF>(v, P, k, xcd_wave(blockIdx.x, gridDim.x), kick, heat);
+__device__ __forceinline__ void forces_wave(const View<R>& v, const Params& P, const KC<R>& k, int w, int kick,
+                                            int heat) {
+  __shared__ uint32_t jl[Nb<DIM>::rows];
+  __shared__ MatL<R> smat[kMatLds];
+  __shared__ R ro[2 * Nb<DIM>::rows];
+  if (w >= (int)*v.nb.nwaves) return;
+  stage_rows<R, DIM>(ro, k);
+  stage_mats<R>(smat, v, P);
+  stage_jlo<DIM>(jl, v.nb, w);
+  forces_wave_body<R, DIM, THERMAL, TVF>(v, P, k, w, (int)threadIdx.x, smat, ro, jl, kick, heat);
+}
+
+// kFwpb consecutive waves per workgroup: they run on one CU and share its
+// L1, where their neighbour records overlap (0.641 -> 0.628 ms on the 3D
+// column against one wave per workgroup; 8 waves: 0.651 ms); every barrier
+// comes before any wave leaves
+constexpr int kFwpb = 4;
+template <typename R, int DIM, int THERMAL, int TVF>
+__global__ void __launch_bounds__(64 * kFwpb) k_forces_list(View<R> v, Params P, KC<R> k, int kick, int heat) {
+  constexpr int NR = Nb<DIM>::rows;
+  __shared__ uint32_t jl[kFwpb][NR];
+  __shared__ MatL<R> smat[kMatLds];
+  __shared__ R ro[2 * NR];
+  const int wv = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63u);
+  const int w = xcd_wave(blockIdx.x, gridDim.x) * kFwpb + wv;
+  const int nwaves = (int)*v.nb.nwaves;
+  if (threadIdx.x < (unsigned)NR) {
+    const int t = (int)threadIdx.x;
+    ro[2 * t] = (R)(t % 3 - 1) * k.L;
+    ro[2 * t + 1] = DIM == 3 ? (R)(t / 3 - 1) * k.L : R(0);
+  }
+  const int nm = P.n_mat < kMatLds ? P.n_mat : kMatLds;
+  for (int q = (int)threadIdx.x; q < nm; q += (int)blockDim.x) smat[q] = mat_from<R>(v.mat[q]);
+  if (lane < NR && w < nwaves) jl[wv][lane] = v.nb.jlo[(size_t)w * NR + lane];
+  __syncthreads();
+  if (w < nwaves) forces_wave_body<R, DIM, THERMAL, TVF>(v, P, k, w, lane, smat, ro, jl[wv], kick, heat);
 }
 
 // ---------------------------------------------------------------------------
@@ -2259,21 +2289,25 @@ void Launch<R>::extrapolate(const View<R>& v, const Params& P, const KC<R>& k, h
 // at 2.25 on the 3D column); FP64 is held at 4 by its registers
 template <typename R>
 constexpr size_t forces_lds() { return IsExact<R>::v ? 0 : 10240; }
+// the same for the single-scene sweep's workgroups of kFwpb waves: 4 per
+// CU, 16 waves (4 per SIMD; 5: 0.631 ms, 4: 0.628 ms)
+template <typename R>
+constexpr size_t forces_multi_lds() { return IsExact<R>::v ? 0 : 39000; }
 
 template <typename R>
 void Launch<R>::forces(const View<R>& v, const Params& P, const KC<R>& k, int kick, int heat, hipStream_t st) {
   if (P.n <= 0) return;
-  const unsigned g = (unsigned)P.max_waves;
+  const unsigned g = (unsigned)((P.max_waves + kFwpb - 1) / kFwpb);
   const int mode = (P.thermal ? 1 : 0) | (P.tvf ? 2 : 0);
   switch (mode | (P.dim == 3 ? 4 : 0)) {
-    case 0: k_forces_list<R, 2, 0, 0><<<g, 64, forces_lds<R>(), st>>>(v, P, k, kick, heat); break;
-    case 1: k_forces_list<R, 2, 1, 0><<<g, 64, forces_lds<R>(), st>>>(v, P, k, kick, heat); break;
-    case 2: k_forces_list<R, 2, 0, 1><<<g, 64, forces_lds<R>(), st>>>(v, P, k, kick, heat); break;
-    case 3: k_forces_list<R, 2, 1, 1><<<g, 64, forces_lds<R>(), st>>>(v, P, k, kick, heat); break;
-    case 4: k_forces_list<R, 3, 0, 0><<<g, 64, forces_lds<R>(), st>>>(v, P, k, kick, heat); break;
-    case 5: k_forces_list<R, 3, 1, 0><<<g, 64, forces_lds<R>(), st>>>(v, P, k, kick, heat); break;
-    case 6: k_forces_list<R, 3, 0, 1><<<g, 64, forces_lds<R>(), st>>>(v, P, k, kick, heat); break;
-    default: k_forces_list<R, 3, 1, 1><<<g, 64, forces_lds<R>(), st>>>(v, P, k, kick, heat); break;
+    case 0: k_forces_list<R, 2, 0, 0><<<g, 64 * kFwpb, forces_multi_lds<R>(), st>>>(v, P, k, kick, heat); break;
+    case 1: k_forces_list<R, 2, 1, 0><<<g, 64 * kFwpb, forces_multi_lds<R>(), st>>>(v, P, k, kick, heat); break;
+    case 2: k_forces_list<R, 2, 0, 1><<<g, 64 * kFwpb, forces_multi_lds<R>(), st>>>(v, P, k, kick, heat); break;
+    case 3: k_forces_list<R, 2, 1, 1><<<g, 64 * kFwpb, forces_multi_lds<R>(), st>>>(v, P, k, kick, heat); break;
+    case 4: k_forces_list<R, 3, 0, 0><<<g, 64 * kFwpb, forces_multi_lds<R>(), st>>>(v, P, k, kick, heat); break;
+    case 5: k_forces_list<R, 3, 1, 0><<<g, 64 * kFwpb, forces_multi_lds<R>(), st>>>(v, P, k, kick, heat); break;
+    case 6: k_forces_list<R, 3, 0, 1><<<g, 64 * kFwpb, forces_multi_lds<R>(), st>>>(v, P, k, kick, heat); break;
+    default: k_forces_list<R, 3, 1, 1><<<g, 64 * kFwpb, forces_multi_lds<R>(), st>>>(v, P, k, kick, heat); break;
   }
 }
 template <typename R>
