@@ -103,6 +103,28 @@ def test_neighbour_capacity_is_a_sticky_error(B):
             B.SphScene(sc, precision=prec, dt=1e-6)
 
 
+def test_overlong_candidate_window_is_an_error(B):
+    """More than 4096 candidates in one stencil row of a wave (the entries
+    hold 12-bit offsets): 4500 fluid particles packed into one cell of a 2D
+    box; the set-up evaluation finishes and reports the capacity bit."""
+    import re
+    sc = S.fluid_box(dim=2, n_side=8, walls=False)
+    rng = np.random.default_rng(3)
+    n = 4500
+    c = sc.x.mean(axis=0)
+    h = 0.45 * sc.dx    # well inside one cell of edge 3 dx
+    x = np.zeros((n, 3))
+    x[:, :2] = c[:2] + rng.uniform(-h, h, size=(n, 2))
+    keep = np.zeros(n, dtype=np.int64)
+    sub = _subset(sc, keep)
+    sub.x = np.ascontiguousarray(x)
+    for prec in (B.SPH_FP32_SWEEP, B.SPH_FP64):
+        with pytest.raises(RuntimeError, match="set-up") as e:
+            B.SphScene(sub, precision=prec, dt=1e-7)
+        bits = int(re.search(r"set-up: (\d+)", str(e.value)).group(1))
+        assert bits & 32, bits
+
+
 def test_fp32_thermal_switching_gates(B):
     """FP32 sweep with conduction and phase switching (temperatures kept away
     from T_t, so the switching decisions are the oracle's)."""
