@@ -1256,33 +1256,20 @@ __device__ __forceinline__ void forces_wave_body(const View<R>& v, const Params&
   });
 }
 
-// one wave per workgroup (the batched sweep)
-template <typename R, int DIM, int THERMAL, int TVF>
-__device__ __forceinline__ void forces_wave(const View<R>& v, const Params& P, const KC<R>& k, int w, int kick,
-                                            int heat) {
-  __shared__ uint32_t jl[Nb<DIM>::rows];
-  __shared__ MatL<R> smat[kMatLds];
-  __shared__ R ro[2 * Nb<DIM>::rows];
-  if (w >= (int)*v.nb.nwaves) return;
-  stage_rows<R, DIM>(ro, k);
-  stage_mats<R>(smat, v, P);
-  stage_jlo<DIM>(jl, v.nb, w);
-  forces_wave_body<R, DIM, THERMAL, TVF>(v, P, k, w, (int)threadIdx.x, smat, ro, jl, kick, heat);
-}
-
 // kFwpb consecutive waves per workgroup: they run on one CU and share its
 // L1, where their neighbour records overlap (0.641 -> 0.628 ms on the 3D
-// column against one wave per workgroup; 8 waves: 0.651 ms); every barrier
-// comes before any wave leaves
+// column against one wave per workgroup; 8 waves: 0.651 ms); group g of
+// the scene's groups, every barrier before any wave leaves
 constexpr int kFwpb = 4;
 template <typename R, int DIM, int THERMAL, int TVF>
-__global__ void __launch_bounds__(64 * kFwpb) k_forces_list(View<R> v, Params P, KC<R> k, int kick, int heat) {
+__device__ __forceinline__ void forces_group(const View<R>& v, const Params& P, const KC<R>& k, int g, int kick,
+                                             int heat) {
   constexpr int NR = Nb<DIM>::rows;
   __shared__ uint32_t jl[kFwpb][NR];
   __shared__ MatL<R> smat[kMatLds];
   __shared__ R ro[2 * NR];
   const int wv = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63u);
-  const int w = xcd_wave(blockIdx.x, gridDim.x) * kFwpb + wv;
+  const int w = g * kFwpb + wv;
   const int nwaves = (int)*v.nb.nwaves;
   if (threadIdx.x < (unsigned)NR) {
     const int t = (int)threadIdx.x;
@@ -1294,6 +1281,11 @@ __global__ void __launch_bounds__(64 * kFwpb) k_forces_list(View<R> v, Params P,
   if (lane < NR && w < nwaves) jl[wv][lane] = v.nb.jlo[(size_t)w * NR + lane];
   __syncthreads();
   if (w < nwaves) forces_wave_body<R, DIM, THERMAL, TVF>(v, P, k, w, lane, smat, ro, jl[wv], kick, heat);
+}
+
+template <typename R, int DIM, int THERMAL, int TVF>
+__global__ void __launch_bounds__(64 * kFwpb) k_forces_list(View<R> v, Params P, KC<R> k, int kick, int heat) {
+  forces_group<R, DIM, THERMAL, TVF>(v, P, k, xcd_wave(blockIdx.x, gridDim.x), kick, heat);
 }
 
 // ---------------------------------------------------------------------------
@@ -1343,14 +1335,18 @@ __global__ void __launch_bounds__(64) k_extrapolate_batch(const Slot<R>* tab, co
   extrapolate_wave<R, DIM>(v, P, k, (int)(blockIdx.x - S.b0), (int)S.nb);
 }
 
+// workgroup q covers the scene blocks kFwpb q .. kFwpb q + kFwpb - 1, all of
+// one scene (b0 and nb are multiples of 8)
 template <typename R, int DIM, int THERMAL, int TVF>
-__global__ void __launch_bounds__(64) k_forces_batch(const Slot<R>* tab, const char* gbase, int ns, int kick,
-                                                     int heat) {
-  const Slot<R>& S = tab[find_slot<R>(tab, ns, blockIdx.x)];
+__global__ void __launch_bounds__(64 * kFwpb) k_forces_batch(const Slot<R>* tab, const char* gbase, int ns, int kick,
+                                                             int heat) {
+  const uint32_t b = blockIdx.x * (uint32_t)kFwpb;
+  const Slot<R>& S = tab[find_slot<R>(tab, ns, b)];
   const View<R> v = slot_view<R>(S, gbase);
   const Params P = S.P;
   const KC<R> k = S.k;
-  forces_wave<R, DIM, THERMAL, TVF>(v, P, k, xcd_wave((int)(blockIdx.x - S.b0), (int)S.nb), kick, heat);
+  forces_group<R, DIM, THERMAL, TVF>(v, P, k, xcd_wave((int)((b - S.b0) / kFwpb), (int)(S.nb / kFwpb)), kick,
+                                     heat);
 }
 
 // start of a step: per-evaluation pair counters cleared, step counter advanced
@@ -2283,14 +2279,11 @@ void Launch<R>::extrapolate(const View<R>& v, const Params& P, const KC<R>& k, h
   if (P.dim == 2) k_extrapolate_list<R, 2><<<g, 64, 0, st>>>(v, P, k);
   else k_extrapolate_list<R, 3><<<g, 64, 0, st>>>(v, P, k);
 }
-// unused dynamic LDS that holds the FP32 force sweep at about 3.5 waves per
-// SIMD: its gathers share the L1, and more waves only evict each other's
-// lines (0.653 ms at 8 waves per SIMD against 0.641 ms at 3.5 and 0.682 ms
-// at 2.25 on the 3D column); FP64 is held at 4 by its registers
-template <typename R>
-constexpr size_t forces_lds() { return IsExact<R>::v ? 0 : 10240; }
-// the same for the single-scene sweep's workgroups of kFwpb waves: 4 per
-// CU, 16 waves (4 per SIMD; 5: 0.631 ms, 4: 0.628 ms)
+// unused dynamic LDS that holds the FP32 force sweep's workgroups of kFwpb
+// waves at 4 per CU (16 waves, 4 per SIMD): the gathers share the L1, and
+// more waves only evict each other's lines (per SIMD, one wave per
+// workgroup: 0.653 ms at 8, 0.641 at 3.5, 0.682 at 2.25; four per workgroup:
+// 0.631 at 5, 0.628 at 4); FP64 is held at 4 by its registers
 template <typename R>
 constexpr size_t forces_multi_lds() { return IsExact<R>::v ? 0 : 39000; }
 
@@ -2323,14 +2316,14 @@ void Launch<R>::batch_sweep(int stage, const Slot<R>* tab, const char* gbase, in
   } else {
     // mode: bit 0 thermal, bit 1 transport-velocity formulation
     switch ((mode & 3) | (dim == 3 ? 4 : 0)) {
-      case 0: k_forces_batch<R, 2, 0, 0><<<blocks, 64, forces_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
-      case 1: k_forces_batch<R, 2, 1, 0><<<blocks, 64, forces_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
-      case 2: k_forces_batch<R, 2, 0, 1><<<blocks, 64, forces_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
-      case 3: k_forces_batch<R, 2, 1, 1><<<blocks, 64, forces_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
-      case 4: k_forces_batch<R, 3, 0, 0><<<blocks, 64, forces_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
-      case 5: k_forces_batch<R, 3, 1, 0><<<blocks, 64, forces_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
-      case 6: k_forces_batch<R, 3, 0, 1><<<blocks, 64, forces_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
-      default: k_forces_batch<R, 3, 1, 1><<<blocks, 64, forces_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
+      case 0: k_forces_batch<R, 2, 0, 0><<<blocks / kFwpb, 64 * kFwpb, forces_multi_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
+      case 1: k_forces_batch<R, 2, 1, 0><<<blocks / kFwpb, 64 * kFwpb, forces_multi_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
+      case 2: k_forces_batch<R, 2, 0, 1><<<blocks / kFwpb, 64 * kFwpb, forces_multi_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
+      case 3: k_forces_batch<R, 2, 1, 1><<<blocks / kFwpb, 64 * kFwpb, forces_multi_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
+      case 4: k_forces_batch<R, 3, 0, 0><<<blocks / kFwpb, 64 * kFwpb, forces_multi_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
+      case 5: k_forces_batch<R, 3, 1, 0><<<blocks / kFwpb, 64 * kFwpb, forces_multi_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
+      case 6: k_forces_batch<R, 3, 0, 1><<<blocks / kFwpb, 64 * kFwpb, forces_multi_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
+      default: k_forces_batch<R, 3, 1, 1><<<blocks / kFwpb, 64 * kFwpb, forces_multi_lds<R>(), st>>>(tab, gbase, ns, kick, heat); break;
     }
   }
 }
