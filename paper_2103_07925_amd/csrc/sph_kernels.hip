@@ -2138,7 +2138,11 @@ __global__ void __launch_bounds__(1024) k_scan_small(uint32_t* in, uint32_t* out
 }
 
 // waves of every x-row of cells (64 particles at most, one row each) and
-// the wave table, in one workgroup; woff[nrows] receives the wave count
+// the wave table; woff[nrows] receives the wave count.  Every workgroup
+// scans the rows' wave counts (one workgroup's work), then writes the
+// table entries of its share of the rows, so that the scattered table
+// stores are spread over kWaveTableBlocks CUs
+constexpr int kWaveTableBlocks = 16;
 __global__ void __launch_bounds__(1024) k_wave_table_small(const uint32_t* cstart, int nx, int64_t nrows,
                                                            uint32_t* woff, WaveInfo* table) {
   const int64_t chunk = (nrows + 1023) / 1024;
@@ -2148,6 +2152,9 @@ __global__ void __launch_bounds__(1024) k_wave_table_small(const uint32_t* cstar
   for (int64_t r = a; r < b; ++r) sum += (cstart[(r + 1) * nx] - cstart[r * nx] + 63u) >> 6;
   uint32_t tot;
   uint32_t w0 = block1024_exclusive_scan(sum, &tot);
+  // this workgroup's threads: [t0, t1)
+  const int t0 = (int)(blockIdx.x * 1024u / gridDim.x), t1 = (int)((blockIdx.x + 1u) * 1024u / gridDim.x);
+  if ((int)threadIdx.x < t0 || (int)threadIdx.x >= t1) return;
   for (int64_t r = a; r < b; ++r) {
     const uint32_t s0 = cstart[r * nx];
     const uint32_t n = cstart[(r + 1) * nx] - s0;
@@ -2162,7 +2169,7 @@ __global__ void __launch_bounds__(1024) k_wave_table_small(const uint32_t* cstar
     }
     w0 += (n + 63u) >> 6;
   }
-  if (threadIdx.x == 0) woff[nrows] = tot;
+  if (threadIdx.x == 0) woff[nrows] = tot;   // only in workgroup 0 (t0 = 0)
 }
 
 // ---------------------------------------------------------------------------
@@ -2197,7 +2204,7 @@ void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsu
 void launch_wave_table(const Params& P, const uint32_t* cstart, uint32_t* wcount, uint32_t* woff, uint32_t* bsum,
                        WaveInfo* table, hipStream_t st) {
   if (P.nrows <= kSmallRows) {
-    k_wave_table_small<<<1, 1024, 0, st>>>(cstart, P.nc[0], P.nrows, woff, table);
+    k_wave_table_small<<<kWaveTableBlocks, 1024, 0, st>>>(cstart, P.nc[0], P.nrows, woff, table);
     return;
   }
   k_row_waves<<<nblk(P.nrows), 256, 0, st>>>(cstart, P.nc[0], P.nrows, wcount);
