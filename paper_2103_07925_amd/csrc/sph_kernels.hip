@@ -1712,7 +1712,16 @@ __global__ void __launch_bounds__(256) k_rank(const uint32_t* key, const uint32_
   }
   const uint32_t my = tid[p];
   uint32_t r = 0;
-  for (uint32_t q = s0; q < s1; ++q) r += (tid[q] < my) ? 1u : 0u;
+  uint32_t q = s0;
+  // eight loads in flight per round (one at a time waits out each load)
+  for (; q + 8u <= s1; q += 8u) {
+    uint32_t t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = tid[q + (uint32_t)u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) r += (t[u] < my) ? 1u : 0u;
+  }
+  for (; q < s1; ++q) r += (tid[q] < my) ? 1u : 0u;
   perm[s0 + r] = src;
 }
 
